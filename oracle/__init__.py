@@ -1,0 +1,207 @@
+"""FP64 CPU oracle for the ORCA step (ctypes wrapper over ``orca_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU
+baseline of the benchmark may use this package; the library path must not.
+It shares no code with the GPU library.  Every scalar parameter is first
+rounded to FP32 (the precision the GPU library receives it in) and then
+widened to double, so both sides start from identical inputs.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "orca_oracle.c")
+_LIB = os.path.join(_HERE, "liborca_oracle.so")
+K_MAX = 64
+NWORK = 8
+WORK_FIELDS = ("candidates", "in_range", "neighbors", "lp2_violations", "lp2_inner",
+               "lp3_used", "lp3_violations", "lp3_inner")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP64, no contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+                               "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _OParams(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("tau", ctypes.c_double), ("rn", ctypes.c_double),
+                ("k", ctypes.c_int32), ("pref_is_goal", ctypes.c_int32),
+                ("f", (ctypes.c_double * 2) * 2), ("eps", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.oracle_halfplane.restype = ctypes.c_int
+        L.oracle_halfplane.argtypes = [ctypes.c_double] * 13 + [ctypes.c_int, dp]
+        L.oracle_lp2.restype = ctypes.c_int
+        L.oracle_lp2.argtypes = [ctypes.c_int, dp, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_double, dp]
+        L.oracle_lp_full.restype = ctypes.c_int
+        L.oracle_lp_full.argtypes = L.oracle_lp2.argtypes
+        L.oracle_knn.restype = ctypes.c_int
+        L.oracle_knn.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_float,
+                                 ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+        L.oracle_step.restype = ctypes.c_int
+        L.oracle_step.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 9 + \
+            [ctypes.POINTER(_OParams)] + [ctypes.c_void_p] * 8
+        L.oracle_step_batched.restype = ctypes.c_int
+        L.oracle_step_batched.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 10 + \
+            [ctypes.c_void_p] + [ctypes.c_void_p] * 6
+        _lib = L
+    return _lib
+
+
+def _f32d(x) -> float:
+    """Round a scalar to FP32, then widen to double."""
+    return float(np.float32(x))
+
+
+def make_params(params) -> _OParams:
+    """Accepts any object with the ``orca_params`` field names."""
+    g = params.get if isinstance(params, dict) else (lambda k: getattr(params, k))
+    p = _OParams()
+    p.dt = _f32d(g("dt"))
+    p.tau = _f32d(g("time_horizon"))
+    p.rn = _f32d(g("neighbor_dist"))
+    p.k = int(g("max_neighbors"))
+    p.pref_is_goal = int(g("pref_is_goal"))
+    f = g("f")
+    for a in range(2):
+        for b in range(2):
+            p.f[a][b] = _f32d(f[a][b])
+    p.eps = _f32d(g("par_eps"))
+    return p
+
+
+def _c(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data
+
+
+def halfplane(pa, va, ra, pb, vb, rb, f, tau, dt, a_before_b=True):
+    """ORCA_{A|B}: returns dict(q, d, u, n, branch) in FP64."""
+    out = (ctypes.c_double * 8)()
+    br = lib().oracle_halfplane(float(pa[0]), float(pa[1]), float(va[0]), float(va[1]), float(ra),
+                                float(pb[0]), float(pb[1]), float(vb[0]), float(vb[1]), float(rb),
+                                float(f), float(tau), float(dt), int(bool(a_before_b)), out)
+    o = np.array(out[:])
+    return {"q": o[0:2], "d": o[2:4], "u": o[4:6], "n": o[6:8], "branch": br}
+
+
+def lp2(lines, vmax, opt, eps=1e-5):
+    """Incremental closest-point LP.  lines: (m, 4) rows (qx, qy, dx, dy).
+    Returns (v, fail) with fail == m when feasible."""
+    lines = np.ascontiguousarray(lines, dtype=np.float64).reshape(-1, 4)
+    v = (ctypes.c_double * 2)()
+    fail = lib().oracle_lp2(lines.shape[0], lines.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                            float(vmax), float(opt[0]), float(opt[1]), float(eps), v)
+    if fail < 0:
+        raise ValueError("oracle_lp2: bad arguments")
+    return np.array(v[:]), fail
+
+
+def lp_full(lines, vmax, opt, eps=1e-5):
+    """LP2, then LP3 when LP2 is infeasible.  Returns (v, fail)."""
+    lines = np.ascontiguousarray(lines, dtype=np.float64).reshape(-1, 4)
+    v = (ctypes.c_double * 2)()
+    fail = lib().oracle_lp_full(lines.shape[0],
+                                lines.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                float(vmax), float(opt[0]), float(opt[1]), float(eps), v)
+    if fail < 0:
+        raise ValueError("oracle_lp_full: bad arguments")
+    return np.array(v[:]), fail
+
+
+def knn(px, py, neighbor_dist, k):
+    """Exact k nearest within the neighbour distance, ties by index."""
+    px, ppx = _c(px, np.float32)
+    py, ppy = _c(py, np.float32)
+    n = px.shape[0]
+    nbr = np.full((n, k), -1, np.int32)
+    cnt = np.zeros(n, np.int32)
+    rc = lib().oracle_knn(n, ppx, ppy, float(np.float32(neighbor_dist)), int(k),
+                          nbr.ctypes.data, cnt.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"oracle_knn failed ({rc})")
+    return nbr, cnt
+
+
+_STATE = ("px", "py", "vx", "vy", "pref_x", "pref_y", "radius", "max_speed")
+
+
+def _state_ptrs(state):
+    g = state.get if isinstance(state, dict) else (lambda k: getattr(state, k))
+    keep = [np.ascontiguousarray(g(k), dtype=np.float32) for k in _STATE]
+    keep.append(np.ascontiguousarray(g("cls"), dtype=np.uint8))
+    return keep, [a.ctypes.data for a in keep]
+
+
+def step(state, params, want_neighbors: bool = False, want_work: bool = False):
+    """One synchronous step from an FP32 state.  Returns FP64 arrays
+    px, py, vx, vy, the status byte (1 = least-penetration fallback used),
+    and optionally the neighbour lists and per-agent work counters."""
+    keep, ptrs = _state_ptrs(state)
+    n = keep[0].shape[0]
+    p = make_params(params)
+    out = {k: np.zeros(n, np.float64) for k in ("px", "py", "vx", "vy")}
+    status = np.zeros(n, np.uint8)
+    nbr = np.full((n, p.k), -1, np.int32) if want_neighbors else None
+    cnt = np.zeros(n, np.int32) if want_neighbors else None
+    work = np.zeros((n, NWORK), np.int64) if want_work else None
+    rc = lib().oracle_step(n, *ptrs, ctypes.byref(p), out["px"].ctypes.data,
+                           out["py"].ctypes.data, out["vx"].ctypes.data, out["vy"].ctypes.data,
+                           status.ctypes.data, nbr.ctypes.data if nbr is not None else None,
+                           cnt.ctypes.data if cnt is not None else None,
+                           work.ctypes.data if work is not None else None)
+    if rc != 0:
+        raise ValueError(f"oracle_step failed ({rc})")
+    out["status"] = status
+    if want_neighbors:
+        out["nbr"] = nbr
+        out["cnt"] = cnt
+    if want_work:
+        out["work"] = work
+    return out
+
+
+def step_batched(state, scene_off, scene_params, want_work: bool = False):
+    """One step of every scene; scene s owns [off[s], off[s+1])."""
+    keep, ptrs = _state_ptrs(state)
+    n = keep[0].shape[0]
+    off = np.ascontiguousarray(scene_off, dtype=np.int32)
+    S = off.shape[0] - 1
+    parr = (_OParams * max(S, 1))()
+    for s in range(S):
+        parr[s] = make_params(scene_params[s])
+    out = {k: np.zeros(n, np.float64) for k in ("px", "py", "vx", "vy")}
+    status = np.zeros(n, np.uint8)
+    work = np.zeros((n, NWORK), np.int64) if want_work else None
+    rc = lib().oracle_step_batched(S, off.ctypes.data, *ptrs, ctypes.addressof(parr),
+                                   out["px"].ctypes.data, out["py"].ctypes.data,
+                                   out["vx"].ctypes.data, out["vy"].ctypes.data,
+                                   status.ctypes.data,
+                                   work.ctypes.data if work is not None else None)
+    if rc != 0:
+        raise ValueError(f"oracle_step_batched failed ({rc})")
+    out["status"] = status
+    if want_work:
+        out["work"] = work
+    return out

@@ -1,0 +1,196 @@
+"""Pins of the oracle's per-agent linear programs.
+
+LP2 (Sec. 3): the permitted velocity closest to the desired velocity, i.e.
+the Euclidean projection of v_pref onto (intersection of half-planes) within
+the speed disc.  It is unique whenever the set is non-empty, so the
+incremental solver must reproduce the projection found by brute force:
+enumerate every point where the optimum can sit (v_pref itself, its
+projection onto each line and onto the circle, every line-line and
+line-circle intersection), keep the feasible ones, take the nearest.
+
+LP3 (Sec. 3, infeasible case): the velocity that least penetrates the
+half-planes.  Its value t* = min_{|v|<=vmax} max_j delta_j(v) is pinned by
+brute force over the points where a min-max optimum can sit (three equal
+penetrations, two equal penetrations on the circle, the circle point
+deepest inside one line).  The minimiser itself is not unique in general
+and is not pinned here.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+
+def rand_lines(rng, m, qscale=2.0):
+    q = rng.uniform(-qscale, qscale, size=(m, 2))
+    ang = rng.uniform(0, 2 * math.pi, size=m)
+    d = np.stack([np.cos(ang), np.sin(ang)], axis=1)
+    return np.concatenate([q, d], axis=1)
+
+
+def penetration(lines, v):
+    """delta_j(v) = det(d_j, q_j - v): positive means line j is violated."""
+    q = lines[:, 0:2]
+    d = lines[:, 2:4]
+    r = q - v[None, :]
+    return d[:, 0] * r[:, 1] - d[:, 1] * r[:, 0]
+
+
+def line_line(a, b):
+    """Intersection of two lines given as (q, d); None when parallel."""
+    qa, da, qb, db = a[0:2], a[2:4], b[0:2], b[2:4]
+    den = da[0] * db[1] - da[1] * db[0]
+    if abs(den) < 1e-12:
+        return None
+    w = qb - qa
+    t = (w[0] * db[1] - w[1] * db[0]) / den
+    return qa + t * da
+
+
+def line_circle(a, r):
+    q, d = a[0:2], a[2:4]
+    b = q @ d
+    c = q @ q - r * r
+    disc = b * b - c
+    if disc < 0:
+        return []
+    s = math.sqrt(disc)
+    return [q + (-b - s) * d, q + (-b + s) * d]
+
+
+def brute_lp2(lines, vmax, opt):
+    cands = [opt.copy()]
+    no = np.linalg.norm(opt)
+    if no > 0:
+        cands.append(opt / no * vmax)
+    for l in lines:
+        q, d = l[0:2], l[2:4]
+        cands.append(q + ((opt - q) @ d) * d)
+        cands.extend(line_circle(l, vmax))
+    for a, b in itertools.combinations(lines, 2):
+        p = line_line(a, b)
+        if p is not None:
+            cands.append(p)
+    best, bestd = None, np.inf
+    for c in cands:
+        if np.linalg.norm(c) > vmax + 1e-9:
+            continue
+        if len(lines) and penetration(lines, c).max() > 1e-9:
+            continue
+        dd = np.linalg.norm(c - opt)
+        if dd < bestd:
+            best, bestd = c, dd
+    return best
+
+
+def brute_lp3_value(lines, vmax):
+    """min over |v| <= vmax of max_j delta_j(v), by candidate enumeration."""
+    m = len(lines)
+    n = np.stack([-lines[:, 3], lines[:, 2]], axis=1)  # inward normals
+    cands = [vmax * n[j] for j in range(m)]
+    # delta_a = delta_b: n_a.(v - q_a) = n_b.(v - q_b)  ->  (n_a - n_b).v = n_a.q_a - n_b.q_b
+    eq = []
+    for a, b in itertools.combinations(range(m), 2):
+        g = n[a] - n[b]
+        h = n[a] @ lines[a, 0:2] - n[b] @ lines[b, 0:2]
+        eq.append((g, h))
+        gl = np.linalg.norm(g)
+        if gl > 1e-12:
+            # intersections of g.v = h with the circle
+            p0 = g * h / (gl * gl)
+            rem = vmax * vmax - p0 @ p0
+            if rem >= 0:
+                t = np.array([-g[1], g[0]]) / gl
+                cands += [p0 + math.sqrt(rem) * t, p0 - math.sqrt(rem) * t]
+    for a, b, c in itertools.combinations(range(m), 3):
+        A = np.array([n[a] - n[b], n[a] - n[c]])
+        y = np.array([n[a] @ lines[a, 0:2] - n[b] @ lines[b, 0:2],
+                      n[a] @ lines[a, 0:2] - n[c] @ lines[c, 0:2]])
+        if abs(np.linalg.det(A)) > 1e-12:
+            cands.append(np.linalg.solve(A, y))
+    best = np.inf
+    for c in cands:
+        if np.linalg.norm(c) <= vmax + 1e-9:
+            best = min(best, penetration(lines, c).max())
+    return best
+
+
+def test_lp2_matches_brute_force(oracle_mod):
+    rng = np.random.default_rng(2024)
+    n_feasible = n_infeasible = 0
+    for it in range(6000):
+        m = int(rng.integers(0, 9))
+        lines = rand_lines(rng, m)
+        vmax = float(rng.uniform(0.5, 3.0))
+        opt = rng.uniform(-3, 3, size=2)
+        v, fail = oracle_mod.lp2(lines, vmax, opt)
+        bf = brute_lp2(lines, vmax, opt)
+        if fail == m:
+            n_feasible += 1
+            assert bf is not None, (it, lines, vmax, opt)
+            assert np.linalg.norm(v - bf) <= 1e-9 * max(1.0, vmax), (it, v, bf)
+            # the feasible output violates no half-plane by more than 1e-9
+            if m:
+                assert penetration(lines, v).max() <= 1e-9
+            assert np.linalg.norm(v) <= vmax * (1 + 1e-12)
+        else:
+            n_infeasible += 1
+            if bf is not None:
+                # only a feasible set of zero width may be missed by the
+                # incremental solver; anything else is a bug
+                margin = -max(penetration(lines, bf).max() if m else -np.inf,
+                              np.linalg.norm(bf) - vmax)
+                assert margin <= 1e-7, (it, margin)
+    assert n_feasible > 1000 and n_infeasible > 1000
+
+
+def test_lp3_value_matches_brute_force(oracle_mod):
+    rng = np.random.default_rng(77)
+    checked = 0
+    for it in range(3000):
+        m = int(rng.integers(2, 8))
+        lines = rand_lines(rng, m, qscale=2.5)
+        vmax = float(rng.uniform(0.5, 2.0))
+        opt = rng.uniform(-2, 2, size=2)
+        v, fail = oracle_mod.lp_full(lines, vmax, opt)
+        if fail == m:
+            continue
+        checked += 1
+        t_or = penetration(lines, v).max()
+        t_bf = brute_lp3_value(lines, vmax)
+        # the projected lines of nearly parallel pairs sit far from the origin,
+        # so the disc interval on them carries cancellation of a few 1e-9
+        assert np.linalg.norm(v) <= vmax * (1 + 1e-8)
+        assert t_or <= t_bf + 1e-9, (it, t_or, t_bf)
+        assert t_or >= t_bf - 1e-9, (it, t_or, t_bf)
+    assert checked > 1000
+
+
+def test_lp2_empty_and_disc_only(oracle_mod):
+    v, fail = oracle_mod.lp2(np.zeros((0, 4)), 1.5, np.array([3.0, 4.0]))
+    assert fail == 0
+    np.testing.assert_allclose(v, [0.9, 1.2], rtol=0, atol=1e-15)
+    v, fail = oracle_mod.lp2(np.zeros((0, 4)), 1.5, np.array([0.3, -0.4]))
+    np.testing.assert_array_equal(v, [0.3, -0.4])
+
+
+def test_lp2_single_line_projection(oracle_mod):
+    # one line through (0, 0.5) pointing +x: permitted side y >= 0.5
+    lines = np.array([[0.0, 0.5, 1.0, 0.0]])
+    v, fail = oracle_mod.lp2(lines, 2.0, np.array([0.7, -1.0]))
+    assert fail == 1
+    np.testing.assert_allclose(v, [0.7, 0.5], atol=1e-15)
+
+
+def test_lp2_parallel_rule(oracle_mod):
+    # two antiparallel lines leaving an empty strip -> infeasible at line 1
+    lines = np.array([[0.0, 0.5, 1.0, 0.0],     # y >= 0.5
+                      [0.0, 0.2, -1.0, 0.0]])   # y <= 0.2
+    v, fail = oracle_mod.lp2(lines, 2.0, np.array([0.0, 0.0]))
+    assert fail == 1
+    # a parallel, redundant line is skipped
+    lines = np.array([[0.0, 0.5, 1.0, 0.0], [0.0, -0.5, 1.0, 0.0]])
+    v, fail = oracle_mod.lp2(lines, 2.0, np.array([0.3, 0.0]))
+    assert fail == 2
+    np.testing.assert_allclose(v, [0.3, 0.5], atol=1e-15)
