@@ -1,0 +1,124 @@
+/*
+ * orca.h -- C ABI of the MI355X (gfx950) ORCA step library, liborca.so.
+ *
+ * The library advances crowds of pedestrians and vehicles by one ORCA step
+ * ("Simulating Crowds and Autonomous Vehicles", Charlton, Montana Gonzalez,
+ * Maddock, Richmond):
+ *   1. uniform-grid spatial partition of the agents (Sec. 1, Sec. 3),
+ *   2. each agent's k nearest neighbours within the neighbour distance
+ *      (Sec. 3: every agent observes the radius, position and velocity of
+ *      nearby agents; Sec. 5: fewer neighbours trade realism for memory),
+ *   3. one ORCA half-plane per neighbour, shifted by the responsibility
+ *      factor f_{A|B} (Fig. 1(b,c), Sec. 3.1),
+ *   4. one small 2D linear program per agent for the permitted velocity
+ *      closest to the desired one (Sec. 3), with the least-penetration
+ *      fallback when the half-planes leave nothing permitted (Sec. 3),
+ *   5. explicit Euler update of every agent from the same step-t state.
+ *
+ * Conventions shared by all entry points
+ *  - Agent arrays are structure-of-arrays, FP32 (class: uint8), length n,
+ *    in the caller's order, and are DEVICE pointers unless stated.
+ *  - Agent class 0 is a pedestrian, 1 a vehicle; f[c_self][c_other] is the
+ *    responsibility agent c_self takes for avoiding c_other.  The paper's
+ *    values are f = {{1/2, 1}, {0, 1/2}} (person-person 1/2, person-car 1,
+ *    car-person 0, car-car 1/2).  All classes run the same code path.
+ *  - The caller owns every buffer, including the workspace; no entry point
+ *    allocates, frees or synchronises.  Work is enqueued on `stream` and
+ *    results are visible in stream order.  Entry points are safe to call
+ *    concurrently on different streams with different workspaces.
+ *  - A workspace must be zero-filled once before its first use (for example
+ *    with orca_workspace_init); the library keeps it reusable after that.
+ *  - Errors: every function returns ORCA_OK (0) or a negative ORCA_E* code.
+ *    Arguments are validated on the host before anything is enqueued; on an
+ *    error nothing is enqueued.  n == 0 is a no-op that returns ORCA_OK.
+ *    NaN/Inf inside agent arrays are not checked and propagate.
+ */
+#ifndef ORCA_H
+#define ORCA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORCA_OK 0
+#define ORCA_EINVAL (-1)     /* null pointer, negative size, bad parameter */
+#define ORCA_EWORKSPACE (-2) /* workspace smaller than orca_workspace_bytes() */
+#define ORCA_EHIP (-3)       /* a HIP launch reported an error */
+#define ORCA_ERANGE (-4)     /* max_neighbors outside 1..ORCA_K_MAX */
+
+#define ORCA_K_MAX 32
+
+/* Per-agent inputs (device pointers, length n, caller order).
+ * pref_x/pref_y hold the goal position when orca_params.pref_is_goal is 1
+ * (desired velocity = (goal - p) * min(max_speed/|goal - p|, 1/dt), zero at
+ * the goal; Sec. 3, Sec. 4) and the desired velocity itself otherwise. */
+typedef struct {
+    const float *px, *py;          /* position [m] */
+    const float *vx, *vy;          /* current velocity [m/s], used as v_opt */
+    const float *pref_x, *pref_y;  /* goal [m] or desired velocity [m/s] */
+    const float *radius;           /* disc radius [m] */
+    const float *max_speed;        /* speed cap [m/s] */
+    const uint8_t *cls;            /* 0 pedestrian, 1 vehicle */
+} orca_agents_in;
+
+/* Per-agent outputs (device pointers, length n, caller order).  They may
+ * alias the corresponding inputs (in-place step).  status is optional
+ * (NULL): 1 where the least-penetration fallback was used, else 0. */
+typedef struct {
+    float *px, *py, *vx, *vy;
+    uint8_t *status;
+} orca_agents_out;
+
+/* Scalar parameters of one scene (host memory for orca_step and
+ * orca_build_grid; device memory, one per scene, for orca_step_batched). */
+typedef struct {
+    float dt;             /* step [s], > 0 */
+    float time_horizon;   /* look-ahead tau [s], > 0 (Sec. 3) */
+    float neighbor_dist;  /* neighbour range R_n [m], > 0 (strict: dist < R_n) */
+    float cell_size;      /* grid cell [m]; 0 selects the library default */
+    int32_t max_neighbors;/* k, 1..ORCA_K_MAX */
+    int32_t pref_is_goal; /* 1: pref_* are goals, 0: desired velocities */
+    float f[2][2];        /* responsibility f[class_self][class_other] (Sec. 3.1) */
+    float par_eps;        /* parallel-line tolerance of the LP, e.g. 1e-5 */
+} orca_params;
+
+/* Bytes of workspace needed for n agents (plain step / grid), or for a
+ * batch whose total agent count is n and scene count n_scenes (batched step;
+ * pass n_scenes = 0 for the plain step).  max_cells bounds the grid cells
+ * (0 selects a default of max(2n, 4096)); when a scene's bounding box would
+ * need more cells the library enlarges the cell size on the device. */
+size_t orca_workspace_bytes(int32_t n, int32_t n_scenes, int32_t max_cells);
+
+/* Zero-fills a workspace on `stream` (a fill kernel, no memset node). */
+int orca_workspace_init(void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Builds the grid and the exact neighbour lists (no velocity update).
+ * nbr (n x k, row-major, nullable): caller indices of the k nearest agents
+ * j != i with |p_j - p_i|^2 < R_n^2, ascending in (squared distance, j),
+ * padded with -1; the squared distance is evaluated in double from the FP32
+ * positions without fused multiply-add, so lists are exactly reproducible.
+ * nbr_count (n, nullable): number of valid entries per agent. */
+int orca_build_grid(const orca_agents_in *in, int32_t n, const orca_params *params,
+                    void *ws, size_t ws_bytes, int32_t *nbr, int32_t *nbr_count,
+                    hipStream_t stream);
+
+/* One ORCA step of one scene (grid, neighbours, half-planes, LP, update). */
+int orca_step(const orca_agents_in *in, const orca_agents_out *out, int32_t n,
+              const orca_params *params, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Human-readable text for a status code (static storage). */
+const char *orca_status_string(int code);
+
+/* Version string of the library build. */
+const char *orca_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ORCA_H */

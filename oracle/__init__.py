@@ -61,7 +61,7 @@ def lib():
                                  ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
         L.oracle_step.restype = ctypes.c_int
         L.oracle_step.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 9 + \
-            [ctypes.POINTER(_OParams)] + [ctypes.c_void_p] * 8
+            [ctypes.POINTER(_OParams)] + [ctypes.c_void_p] * 10
         L.oracle_step_batched.restype = ctypes.c_int
         L.oracle_step_batched.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 10 + \
             [ctypes.c_void_p] + [ctypes.c_void_p] * 6
@@ -154,10 +154,12 @@ def _state_ptrs(state):
     return keep, [a.ctypes.data for a in keep]
 
 
-def step(state, params, want_neighbors: bool = False, want_work: bool = False):
+def step(state, params, want_neighbors: bool = False, want_work: bool = False,
+         want_lines: bool = False):
     """One synchronous step from an FP32 state.  Returns FP64 arrays
     px, py, vx, vy, the status byte (1 = least-penetration fallback used),
-    and optionally the neighbour lists and per-agent work counters."""
+    and optionally the neighbour lists, per-agent work counters, and each
+    agent's half-planes (n, k, 4) with its desired velocity (n, 2)."""
     keep, ptrs = _state_ptrs(state)
     n = keep[0].shape[0]
     p = make_params(params)
@@ -166,11 +168,17 @@ def step(state, params, want_neighbors: bool = False, want_work: bool = False):
     nbr = np.full((n, p.k), -1, np.int32) if want_neighbors else None
     cnt = np.zeros(n, np.int32) if want_neighbors else None
     work = np.zeros((n, NWORK), np.int64) if want_work else None
+    lines = np.zeros((n, p.k, 4), np.float64) if want_lines else None
+    pref = np.zeros((n, 2), np.float64) if want_lines else None
+    if want_lines and not want_neighbors:
+        cnt = np.zeros(n, np.int32)
     rc = lib().oracle_step(n, *ptrs, ctypes.byref(p), out["px"].ctypes.data,
                            out["py"].ctypes.data, out["vx"].ctypes.data, out["vy"].ctypes.data,
                            status.ctypes.data, nbr.ctypes.data if nbr is not None else None,
                            cnt.ctypes.data if cnt is not None else None,
-                           work.ctypes.data if work is not None else None)
+                           work.ctypes.data if work is not None else None,
+                           lines.ctypes.data if lines is not None else None,
+                           pref.ctypes.data if pref is not None else None)
     if rc != 0:
         raise ValueError(f"oracle_step failed ({rc})")
     out["status"] = status
@@ -179,6 +187,10 @@ def step(state, params, want_neighbors: bool = False, want_work: bool = False):
         out["cnt"] = cnt
     if want_work:
         out["work"] = work
+    if want_lines:
+        out["lines"] = lines
+        out["pref"] = pref
+        out["cnt"] = cnt
     return out
 
 

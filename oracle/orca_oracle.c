@@ -392,7 +392,9 @@ static int ogrid_build(ogrid *g, int n, const float *px, const float *py, double
         if (py[i] < y0) y0 = py[i];
         if (py[i] > y1) y1 = py[i];
     }
-    double cs = rn > 0.0 ? rn : 1.0;
+    /* slightly wider than R_n so that rounding of the cell coordinates can
+     * never push an in-range pair more than one cell apart */
+    double cs = (rn > 0.0 ? rn : 1.0) * (1.0 + 1e-6);
     for (;;) {
         g->nx = (int64_t)floor((x1 - x0) / cs) + 1;
         g->ny = (int64_t)floor((y1 - y0) / cs) + 1;
@@ -504,12 +506,15 @@ int oracle_knn(int n, const float *px, const float *py, float neighbor_dist, int
 /* work (nullable, n x 8): candidates examined, in-range count, neighbours  */
 /* used, LP2 violated lines, LP2 inner iterations, LP3 used, LP3 violated   */
 /* lines, LP3 inner iterations.                                             */
+/* lines_out (nullable, n x k x 4): each agent's half-planes (q, d), zero   */
+/* past its neighbour count; pref_out (nullable, n x 2): desired velocity.  */
 /* ------------------------------------------------------------------------ */
 int oracle_step(int n, const float *px, const float *py, const float *vx, const float *vy,
                 const float *pref_x, const float *pref_y, const float *radius,
                 const float *max_speed, const uint8_t *cls, const oparams *prm,
                 double *opx, double *opy, double *ovx, double *ovy, uint8_t *status,
-                int32_t *nbr_out, int32_t *cnt_out, int64_t *work)
+                int32_t *nbr_out, int32_t *cnt_out, int64_t *work, double *lines_out,
+                double *pref_out)
 {
     if (n < 0 || !prm || prm->k < 1 || prm->k > ORACLE_K_MAX) return -1;
     if (!(prm->dt > 0.0) || !(prm->tau > 0.0) || !(prm->rn > 0.0)) return -1;
@@ -577,6 +582,20 @@ int oracle_step(int n, const float *px, const float *py, const float *vx, const 
             if (nbr_out) memcpy(nbr_out + (int64_t)i * k, nb, (size_t)k * sizeof(int32_t));
             if (cnt_out) cnt_out[i] = m;
             if (work) memcpy(work + (int64_t)i * ORACLE_NWORK, w, sizeof(w));
+            if (lines_out) {
+                double *lo = lines_out + (int64_t)i * k * 4;
+                for (int s = 0; s < k; ++s) {
+                    const int ok = s < m;
+                    lo[4 * s + 0] = ok ? L[s].qx : 0.0;
+                    lo[4 * s + 1] = ok ? L[s].qy : 0.0;
+                    lo[4 * s + 2] = ok ? L[s].dx : 0.0;
+                    lo[4 * s + 3] = ok ? L[s].dy : 0.0;
+                }
+            }
+            if (pref_out) {
+                pref_out[2 * i] = prx;
+                pref_out[2 * i + 1] = pry;
+            }
         }
         free(buf);
     }
@@ -600,7 +619,8 @@ int oracle_step_batched(int n_scenes, const int32_t *off, const float *px, const
         const int rc = oracle_step(n, px + a, py + a, vx + a, vy + a, pref_x + a, pref_y + a,
                                    radius + a, max_speed + a, cls + a, &prm[s], opx + a,
                                    opy + a, ovx + a, ovy + a, status ? status + a : NULL, NULL,
-                                   NULL, work ? work + (int64_t)a * ORACLE_NWORK : NULL);
+                                   NULL, work ? work + (int64_t)a * ORACLE_NWORK : NULL, NULL,
+                                   NULL);
         if (rc != 0) return rc;
     }
     return 0;

@@ -1,0 +1,199 @@
+// C ABI of liborca.so: argument validation, workspace layout and dispatch.
+// Nothing here allocates or synchronises; every launch goes on the caller's
+// stream.
+#include "orca_internal.h"
+
+#include <math.h>
+
+namespace orca {
+
+namespace {
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+}  // namespace
+
+Layout make_layout(int64_t n, int64_t n_scenes, int64_t max_cells)
+{
+    Layout L{};
+    if (max_cells <= 0) max_cells = default_max_cells(n);
+    const int64_t S = n_scenes > 0 ? n_scenes : 1;
+    L.n = n;
+    L.n_scenes = S;
+    L.max_cells = max_cells;
+    L.n_tiles = (max_cells + 1 + kScanTile - 1) / kScanTile;
+    size_t o = 0;
+    L.meta = o;
+    o = align_up(o + sizeof(GridMeta) * (size_t)S);
+    L.partial = o;
+    o = align_up(o + sizeof(float4) * (size_t)kBboxBlocks * (size_t)S);
+    L.cell = o;
+    o = align_up(o + sizeof(uint32_t) * (size_t)n);
+    L.rank = o;
+    o = align_up(o + sizeof(uint32_t) * (size_t)n);
+    L.count = o;
+    o = align_up(o + sizeof(uint32_t) * (size_t)(max_cells + 1));
+    L.start = o;
+    o = align_up(o + sizeof(uint32_t) * (size_t)(max_cells + 1));
+    L.tiles = o;
+    o = align_up(o + sizeof(uint32_t) * (size_t)(L.n_tiles + 1));
+    L.s0 = o;
+    o = align_up(o + sizeof(float4) * (size_t)n);
+    L.s1 = o;
+    o = align_up(o + sizeof(float4) * (size_t)n);
+    L.total = o;
+    return L;
+}
+
+Work bind(const Layout &L, void *ws)
+{
+    char *b = (char *)ws;
+    Work w;
+    w.meta = (GridMeta *)(b + L.meta);
+    w.partial = (float4 *)(b + L.partial);
+    w.cell = (uint32_t *)(b + L.cell);
+    w.rank = (uint32_t *)(b + L.rank);
+    w.count = (uint32_t *)(b + L.count);
+    w.start = (uint32_t *)(b + L.start);
+    w.tiles = (uint32_t *)(b + L.tiles);
+    w.s0 = (float4 *)(b + L.s0);
+    w.s1 = (float4 *)(b + L.s1);
+    return w;
+}
+
+namespace {
+
+// The workspace size fixes max_cells for a given n: the largest cell count
+// whose layout still fits, so the caller only has to pass the byte size.
+int64_t max_cells_for(int64_t n, int64_t n_scenes, size_t ws_bytes)
+{
+    const Layout base = make_layout(n, n_scenes, 1);
+    if (base.total > ws_bytes) return 0;
+    int64_t lo = 1, hi = 1;
+    while (make_layout(n, n_scenes, hi * 2).total <= ws_bytes && hi < (int64_t)1 << 30) hi *= 2;
+    hi *= 2;
+    while (hi - lo > 1) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (make_layout(n, n_scenes, mid).total <= ws_bytes)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+bool finite_pos(float v) { return isfinite(v) && v > 0.0f; }
+
+int check_params(const orca_params *p)
+{
+    if (!p) return ORCA_EINVAL;
+    if (p->max_neighbors < 1 || p->max_neighbors > ORCA_K_MAX) return ORCA_ERANGE;
+    if (!finite_pos(p->dt) || !finite_pos(p->time_horizon) || !finite_pos(p->neighbor_dist))
+        return ORCA_EINVAL;
+    if (!(p->cell_size >= 0.0f) || !isfinite(p->cell_size)) return ORCA_EINVAL;
+    if (!(p->par_eps >= 0.0f) || !isfinite(p->par_eps)) return ORCA_EINVAL;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            if (!isfinite(p->f[a][b])) return ORCA_EINVAL;
+    if (p->pref_is_goal != 0 && p->pref_is_goal != 1) return ORCA_EINVAL;
+    return ORCA_OK;
+}
+
+int check_in(const orca_agents_in *in)
+{
+    if (!in || !in->px || !in->py || !in->vx || !in->vy || !in->pref_x || !in->pref_y ||
+        !in->radius || !in->max_speed || !in->cls)
+        return ORCA_EINVAL;
+    return ORCA_OK;
+}
+
+int check_out(const orca_agents_out *out)
+{
+    if (!out || !out->px || !out->py || !out->vx || !out->vy) return ORCA_EINVAL;
+    return ORCA_OK;
+}
+
+// Cell count that keeps the grid within what the 32-bit indices address.
+constexpr int64_t kMaxCellsCap = (int64_t)1 << 30;
+
+int prepare(int32_t n, const orca_params *params, void *ws, size_t ws_bytes, Layout &L)
+{
+    if (n < 0) return ORCA_EINVAL;
+    const int rc = check_params(params);
+    if (rc != ORCA_OK) return rc;
+    if (n == 0) return ORCA_OK;
+    if (!ws) return ORCA_EINVAL;
+    int64_t mc = max_cells_for(n, 0, ws_bytes);
+    if (mc <= 0) return ORCA_EWORKSPACE;
+    if (mc > kMaxCellsCap) mc = kMaxCellsCap;
+    L = make_layout(n, 0, mc);
+    if (L.total > ws_bytes) return ORCA_EWORKSPACE;
+    return ORCA_OK;
+}
+
+}  // namespace
+}  // namespace orca
+
+using namespace orca;
+
+extern "C" {
+
+size_t orca_workspace_bytes(int32_t n, int32_t n_scenes, int32_t max_cells)
+{
+    if (n < 0 || n_scenes < 0 || max_cells < 0) return 0;
+    return make_layout(n, n_scenes, max_cells).total;
+}
+
+int orca_workspace_init(void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!ws && ws_bytes) return ORCA_EINVAL;
+    if (launch_fill_zero(ws, ws_bytes, stream) != hipSuccess) return ORCA_EHIP;
+    return ORCA_OK;
+}
+
+int orca_build_grid(const orca_agents_in *in, int32_t n, const orca_params *params, void *ws,
+                    size_t ws_bytes, int32_t *nbr, int32_t *nbr_count, hipStream_t stream)
+{
+    Layout L{};
+    int rc = prepare(n, params, ws, ws_bytes, L);
+    if (rc != ORCA_OK || n == 0) return rc;
+    rc = check_in(in);
+    if (rc != ORCA_OK) return rc;
+    const Work w = bind(L, ws);
+    if (launch_grid_build(*in, n, *params, L, w, stream) != hipSuccess) return ORCA_EHIP;
+    if (nbr || nbr_count) {
+        if (launch_knn_export(*in, n, *params, L, w, nbr, nbr_count, stream) != hipSuccess)
+            return ORCA_EHIP;
+    }
+    return ORCA_OK;
+}
+
+int orca_step(const orca_agents_in *in, const orca_agents_out *out, int32_t n,
+              const orca_params *params, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    Layout L{};
+    int rc = prepare(n, params, ws, ws_bytes, L);
+    if (rc != ORCA_OK || n == 0) return rc;
+    rc = check_in(in);
+    if (rc != ORCA_OK) return rc;
+    rc = check_out(out);
+    if (rc != ORCA_OK) return rc;
+    const Work w = bind(L, ws);
+    if (launch_grid_build(*in, n, *params, L, w, stream) != hipSuccess) return ORCA_EHIP;
+    if (launch_step(*in, *out, n, *params, L, w, stream) != hipSuccess) return ORCA_EHIP;
+    return ORCA_OK;
+}
+
+const char *orca_status_string(int code)
+{
+    switch (code) {
+    case ORCA_OK: return "ok";
+    case ORCA_EINVAL: return "invalid argument";
+    case ORCA_EWORKSPACE: return "workspace too small";
+    case ORCA_EHIP: return "HIP launch error";
+    case ORCA_ERANGE: return "max_neighbors outside 1..ORCA_K_MAX";
+    default: return "unknown status";
+    }
+}
+
+const char *orca_version(void) { return "orca-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,309 @@
+// Uniform-grid build for one scene: bounding box -> cell keys -> counting sort
+// -> cell-ordered SoA copy.  The grid only bounds which agents are examined as
+// neighbour candidates (Sec. 1 and Sec. 3 use a grid spatial partition for
+// the "nearby agents" query); the neighbour set itself is defined exactly
+// and does not depend on the cell size.
+#include "orca_internal.h"
+
+#include <math.h>
+
+namespace orca {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ float wave_min(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+__device__ __forceinline__ float wave_max(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// Block-wide (min x, min y, max x, max y).  Result valid in thread 0.
+__device__ float4 block_bbox(float4 b)
+{
+    __shared__ float4 red[kBlock / kWave];
+    b.x = wave_min(b.x);
+    b.y = wave_min(b.y);
+    b.z = wave_max(b.z);
+    b.w = wave_max(b.w);
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    if (lane == 0) red[wid] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < kBlock / kWave; ++k) {
+            b.x = fminf(b.x, red[k].x);
+            b.y = fminf(b.y, red[k].y);
+            b.z = fmaxf(b.z, red[k].z);
+            b.w = fmaxf(b.w, red[k].w);
+        }
+    }
+    return b;
+}
+
+// (1) partial bounding boxes; also clears the cell histogram for (3).
+__global__ __launch_bounds__(kBlock) void k_bbox_partial(const float *__restrict__ px,
+                                                         const float *__restrict__ py, int n,
+                                                         float4 *__restrict__ partial,
+                                                         uint32_t *__restrict__ count,
+                                                         int count_len)
+{
+    float4 b = make_float4(INFINITY, INFINITY, -INFINITY, -INFINITY);
+    const int stride = gridDim.x * kBlock;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+        const float x = px[i], y = py[i];
+        b.x = fminf(b.x, x);
+        b.y = fminf(b.y, y);
+        b.z = fmaxf(b.z, x);
+        b.w = fmaxf(b.w, y);
+    }
+    for (int c = blockIdx.x * kBlock + threadIdx.x; c < count_len; c += stride) count[c] = 0u;
+    b = block_bbox(b);
+    if (threadIdx.x == 0) partial[blockIdx.x] = b;
+}
+
+// (2) one block: final bounding box and grid geometry.
+//   m  = stencil radius in cells, ceil(R_n / requested cell size)
+//   cs = max(requested, R_n / m) * (1 + 1e-5), so that m * cs > R_n with a
+//        margin far above the rounding of the FP64 cell coordinates
+//   the cell size grows (and m is re-derived) until nx * ny <= max_cells.
+__global__ __launch_bounds__(kBlock) void k_grid_setup(const float4 *__restrict__ partial,
+                                                       int n_partial, float rn, float cs_req,
+                                                       int max_cells, int n,
+                                                       GridMeta *__restrict__ meta)
+{
+    float4 b = make_float4(INFINITY, INFINITY, -INFINITY, -INFINITY);
+    for (int k = threadIdx.x; k < n_partial; k += kBlock) {
+        const float4 q = partial[k];
+        b.x = fminf(b.x, q.x);
+        b.y = fminf(b.y, q.y);
+        b.z = fmaxf(b.z, q.z);
+        b.w = fmaxf(b.w, q.w);
+    }
+    b = block_bbox(b);
+    if (threadIdx.x != 0) return;
+    // non-finite boxes (NaN/Inf positions) collapse to a single cell
+    const bool finite = isfinite(b.x) && isfinite(b.y) && isfinite(b.z) && isfinite(b.w);
+    const double w = finite ? (double)b.z - (double)b.x : 0.0;
+    const double h = finite ? (double)b.w - (double)b.y : 0.0;
+    double c0 = cs_req > 0.0f ? (double)cs_req : (double)rn;
+    int m = 1;
+    double cs = c0, fx = 0.0, fy = 0.0;
+    for (int it = 0; it < 200; ++it) {
+        m = (int)ceil((double)rn / c0 - 1e-6);
+        if (m < 1) m = 1;
+        cs = fmax(c0, (double)rn / m) * (1.0 + 1e-5);
+        fx = floor(w / cs) + 1.0;
+        fy = floor(h / cs) + 1.0;
+        if (fx * fy <= (double)max_cells) break;
+        c0 *= 1.25;
+    }
+    if (!(fx * fy <= (double)max_cells)) {
+        // unreachable for finite extents below ~1e19 cell sizes: one cell
+        // holding everything is slow but still exact
+        m = 1;
+        fx = 1.0;
+        fy = 1.0;
+        cs = fmax(w, h) + (double)rn + 1.0;
+    }
+    GridMeta g;
+    g.x0 = finite ? b.x : 0.0f;
+    g.y0 = finite ? b.y : 0.0f;
+    g.cs = (float)cs;
+    g.rn = rn;
+    g.nx = (int)fx;
+    g.ny = (int)fy;
+    g.m = m;
+    g.n_cells = g.nx * g.ny;
+    g.inv_cs = 1.0 / cs;
+    g.rn2 = (double)rn * (double)rn;
+    g.cell_base = 0;
+    g.agent_base = 0;
+    g.n = n;
+    g.seg_end = (uint32_t)n;
+    *meta = g;
+}
+
+// (3) cell key and rank inside the cell (atomic counting).
+__global__ __launch_bounds__(kBlock) void k_cell_count(const float *__restrict__ px,
+                                                       const float *__restrict__ py, int n,
+                                                       const GridMeta *__restrict__ meta,
+                                                       uint32_t *__restrict__ cell,
+                                                       uint32_t *__restrict__ rank,
+                                                       uint32_t *__restrict__ count)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const GridMeta g = *meta;
+    const int cx = cell_axis(px[i], g.x0, g.inv_cs, g.nx);
+    const int cy = cell_axis(py[i], g.y0, g.inv_cs, g.ny);
+    const uint32_t c = (uint32_t)(cx + g.nx * cy);
+    cell[i] = c;
+    rank[i] = atomicAdd(&count[c], 1u);
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
+{
+    const int lane = threadIdx.x % kWave;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t t = __shfl_up(v, o, kWave);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Exclusive block scan of one value per thread; returns the exclusive prefix
+// and writes the block total to *total (all threads).
+__device__ uint32_t block_excl_scan(uint32_t v, uint32_t *total)
+{
+    __shared__ uint32_t wsum[kBlock / kWave];
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    const uint32_t inc = wave_incl_scan(v);
+    if (lane == kWave - 1) wsum[wid] = inc;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < kBlock / kWave; ++k) {
+        if (k < wid) base += wsum[k];
+        tot += wsum[k];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + inc - v;
+}
+
+constexpr int kPer = kScanTile / kBlock;  // 8 cells per thread
+
+// (4a) per-tile sums of the histogram.
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t *__restrict__ count,
+                                                        const GridMeta *__restrict__ meta,
+                                                        uint32_t *__restrict__ tiles)
+{
+    const int n_cells = meta->n_cells;
+    const int base = blockIdx.x * kScanTile;
+    if (base >= n_cells) return;
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int c = base + threadIdx.x * kPer + k;
+        if (c < n_cells) s += count[c];
+    }
+    uint32_t tot;
+    block_excl_scan(s, &tot);
+    if (threadIdx.x == 0) tiles[blockIdx.x] = tot;
+}
+
+// (4b) one block: exclusive scan of the tile sums, in place.
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(uint32_t *__restrict__ tiles,
+                                                       const GridMeta *__restrict__ meta)
+{
+    const int nt = (meta->n_cells + kScanTile - 1) / kScanTile;
+    uint32_t carry = 0;
+    for (int b = 0; b < nt; b += kBlock) {
+        const int t = b + threadIdx.x;
+        const uint32_t v = t < nt ? tiles[t] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(v, &tot);
+        if (t < nt) tiles[t] = carry + ex;
+        carry += tot;
+        __syncthreads();
+    }
+}
+
+// (4c) exclusive scan inside each tile, offset by the tile's prefix.
+__global__ __launch_bounds__(kBlock) void k_scan_apply(const uint32_t *__restrict__ count,
+                                                       const uint32_t *__restrict__ tiles,
+                                                       const GridMeta *__restrict__ meta,
+                                                       uint32_t *__restrict__ start)
+{
+    const GridMeta g = *meta;
+    const int base = blockIdx.x * kScanTile;
+    if (base >= g.n_cells) return;
+    uint32_t v[kPer];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int c = base + threadIdx.x * kPer + k;
+        v[k] = c < g.n_cells ? count[c] : 0u;
+        s += v[k];
+    }
+    uint32_t tot;
+    uint32_t run = tiles[blockIdx.x] + block_excl_scan(s, &tot);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int c = base + threadIdx.x * kPer + k;
+        if (c < g.n_cells) start[c] = run;
+        run += v[k];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) start[g.n_cells] = (uint32_t)g.n;
+}
+
+// (5) scatter into cell order: position = start[cell] + rank.
+__global__ __launch_bounds__(kBlock) void k_scatter(orca_agents_in in, int n,
+                                                    const uint32_t *__restrict__ cell,
+                                                    const uint32_t *__restrict__ rank,
+                                                    const uint32_t *__restrict__ start,
+                                                    float4 *__restrict__ s0,
+                                                    float4 *__restrict__ s1)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t pos = start[cell[i]] + rank[i];
+    if (pos >= (uint32_t)n) return;  // cannot happen for a consistent histogram
+    s0[pos] = make_float4(in.px[i], in.py[i], __int_as_float(i), in.radius[i]);
+    s1[pos] = make_float4(in.vx[i], in.vy[i], __int_as_float((int)in.cls[i]), 0.0f);
+}
+
+__global__ void k_fill_zero(uint4 *p, size_t n16)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n16; k += stride)
+        p[k] = make_uint4(0, 0, 0, 0);
+}
+
+}  // namespace
+
+hipError_t launch_grid_build(const orca_agents_in &in, int n, const orca_params &p,
+                             const Layout &L, const Work &w, hipStream_t stream)
+{
+    const int nb = (int)((n + kBlock - 1) / kBlock);
+    const int nbb = nb < kBboxBlocks ? nb : kBboxBlocks;
+    const int count_len = (int)L.max_cells;
+    hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(kBlock), 0, stream, in.px, in.py, n,
+                       w.partial, w.count, count_len);
+    hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(kBlock), 0, stream, w.partial, nbb,
+                       p.neighbor_dist, p.cell_size, count_len, n, w.meta);
+    hipLaunchKernelGGL(k_cell_count, dim3(nb), dim3(kBlock), 0, stream, in.px, in.py, n, w.meta,
+                       w.cell, w.rank, w.count);
+    const int nt = (int)L.n_tiles;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nt), dim3(kBlock), 0, stream, w.count, w.meta, w.tiles);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kBlock), 0, stream, w.tiles, w.meta);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(kBlock), 0, stream, w.count, w.tiles, w.meta,
+                       w.start);
+    hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, stream, in, n, w.cell, w.rank,
+                       w.start, w.s0, w.s1);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(void *ws, size_t bytes, hipStream_t stream)
+{
+    const size_t n16 = bytes / 16;
+    if (n16) {
+        size_t blocks = (n16 + 255) / 256;
+        if (blocks > 4096) blocks = 4096;
+        hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, stream, (uint4 *)ws,
+                           n16);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace orca

@@ -1,0 +1,491 @@
+// Fused ORCA step for one scene on gfx950: one lane per agent, agents taken in
+// cell order so that the lanes of a wavefront share neighbour candidates.
+//
+//   kNN      exact k nearest (squared distance in FP64 without contraction,
+//            ties by caller index) over the rows of the (2m+1)^2 cell stencil;
+//            each stencil row is one contiguous range of the cell-ordered copy
+//   ORCA     one half-plane per neighbour (Fig. 1(b,c), Sec. 3.1), computed
+//            without divergent branches: the arc, leg and overlap forms are
+//            all evaluated and selected, so pedestrians and vehicles run the
+//            same instructions (Sec. 3.1)
+//   LP2      incremental closest-point LP over the half-planes and the speed
+//            disc (Sec. 3)
+//   LP3      least-penetration fallback when LP2 is infeasible (Sec. 3)
+//   update   v' = LP result, p' = p + v' dt, written in caller order
+//
+// The half-planes of a lane live in LDS, one column per lane
+// ([k][block] float4 = (q.x, q.y, d.x, d.y)), so the rolled LP loops can index
+// them dynamically without scratch memory.
+#include "orca_internal.h"
+
+#include <limits.h>
+#include <math.h>
+
+namespace orca {
+namespace {
+
+constexpr int kStepBlock = 128;
+
+struct StepArgs {
+    orca_agents_in in;
+    orca_agents_out out;
+    const GridMeta *meta;
+    const uint32_t *start;
+    const float4 *s0;
+    const float4 *s1;
+    int n;
+    int k;
+    float dt, tau, eps;
+    int pref_is_goal;
+    float f00, f01, f10, f11;
+    int32_t *nbr;   // knn export only
+    int32_t *cnt;
+};
+
+__device__ __forceinline__ float det2(float ax, float ay, float bx, float by)
+{
+    return ax * by - ay * bx;
+}
+
+// Squared distance in double from FP32 positions, each operation rounded
+// separately (no fused multiply-add): the neighbour order is defined on it.
+__device__ __forceinline__ double nb_key(float xi, float yi, float xj, float yj)
+{
+#pragma clang fp contract(off)
+    const double dx = (double)xj - (double)xi;
+    const double dy = (double)yj - (double)yi;
+    return dx * dx + dy * dy;
+}
+
+// Exact k-nearest selection into a sorted register list of capacity K.
+// Returns the number of entries found (<= K).
+template <int K>
+__device__ __forceinline__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
+                                          const float4 *__restrict__ s0, float xi, float yi,
+                                          int self, double (&key)[K], int (&jj)[K],
+                                          int (&pos)[K])
+{
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        key[q] = INFINITY;
+        jj[q] = INT_MAX;
+        pos[q] = -1;
+    }
+    const int cx = cell_axis(xi, g.x0, g.inv_cs, g.nx);
+    const int cy = cell_axis(yi, g.y0, g.inv_cs, g.ny);
+    const int ylo = cy - g.m < 0 ? 0 : cy - g.m;
+    const int yhi = cy + g.m > g.ny - 1 ? g.ny - 1 : cy + g.m;
+    const int xlo = cx - g.m < 0 ? 0 : cx - g.m;
+    const int xhi = cx + g.m > g.nx - 1 ? g.nx - 1 : cx + g.m;
+    for (int yy = ylo; yy <= yhi; ++yy) {
+        const int row = g.cell_base + yy * g.nx;
+        const uint32_t a = start[row + xlo];
+        uint32_t b = start[row + xhi + 1];
+        if (b > g.seg_end) b = g.seg_end;  // defensive: stay inside the scene
+        for (uint32_t t = a; t < b; ++t) {
+            const float4 c = s0[t];
+            const int j = __float_as_int(c.z);
+            const double kk = nb_key(xi, yi, c.x, c.y);
+            const bool better = kk < key[K - 1] || (kk == key[K - 1] && j < jj[K - 1]);
+            if (kk < g.rn2 && j != self && better) {
+                // insertion from the tail: slot q takes slot q-1 while the
+                // candidate is smaller than it, else the candidate (once)
+                bool lt_q = true;
+#pragma unroll
+                for (int q = K - 1; q > 0; --q) {
+                    const bool lt_p = kk < key[q - 1] || (kk == key[q - 1] && j < jj[q - 1]);
+                    if (lt_p) {
+                        key[q] = key[q - 1];
+                        jj[q] = jj[q - 1];
+                        pos[q] = pos[q - 1];
+                    } else if (lt_q) {
+                        key[q] = kk;
+                        jj[q] = j;
+                        pos[q] = (int)t;
+                    }
+                    lt_q = lt_p;
+                }
+                if (lt_q) {
+                    key[0] = kk;
+                    jj[0] = j;
+                    pos[0] = (int)t;
+                }
+            }
+        }
+    }
+    int found = 0;
+#pragma unroll
+    for (int q = 0; q < K; ++q) found += pos[q] >= 0 ? 1 : 0;
+    return found;
+}
+
+// ORCA_{A|B} as (q.x, q.y, d.x, d.y); permitted side det(d, v - q) >= 0.
+// P = p_B - p_A, V = v_A - v_B, R = r_A + r_B.
+//  - not overlapping: w = V - P/tau; the cutoff arc is nearest when the angle
+//    between w and -P is below arccos(R/|P|), else the left leg (det(P,w) > 0)
+//    or the right leg; u is the shortest vector from V to the boundary and n
+//    the outward normal there.
+//  - overlapping (|P| <= R): the horizon becomes dt and only the disc is used;
+//    w = 0 takes the normal (+1, 0) if A's caller index is the smaller one,
+//    else (-1, 0).
+//  - q = v_A + f u, d = (n.y, -n.x).
+__device__ __forceinline__ float4 halfplane(float pax, float pay, float vax, float vay, float ra,
+                                            float pbx, float pby, float vbx, float vby, float rb,
+                                            float f, float inv_tau, float inv_dt, bool a_first)
+{
+    const float Px = pbx - pax, Py = pby - pay;
+    const float Vx = vax - vbx, Vy = vay - vby;
+    const float R = ra + rb;
+    const float dist2 = Px * Px + Py * Py;
+    const float R2 = R * R;
+    const bool overlap = !(dist2 > R2);
+    const float it = overlap ? inv_dt : inv_tau;
+    const float wx = Vx - Px * it, wy = Vy - Py * it;
+    const float w2 = wx * wx + wy * wy;
+    const float wp = wx * Px + wy * Py;
+    const bool arc = overlap || (wp < 0.0f && wp * wp > R2 * w2);
+    // disc (cutoff arc / overlap) form
+    const bool wz = !(w2 > 0.0f);
+    const float wl = sqrtf(w2);
+    const float iwl = wz ? 0.0f : 1.0f / wl;
+    const float anx = wz ? (a_first ? 1.0f : -1.0f) : wx * iwl;
+    const float any = wz ? 0.0f : wy * iwl;
+    const float ul = R * it - wl;
+    // leg form
+    const float leg = sqrtf(fmaxf(dist2 - R2, 0.0f));
+    const float id2 = overlap ? 0.0f : 1.0f / dist2;
+    const bool left = det2(Px, Py, wx, wy) > 0.0f;
+    const float sR = left ? R : -R;
+    const float ex = (Px * leg - Py * sR) * id2;
+    const float ey = (Px * sR + Py * leg) * id2;
+    const float lnx = left ? -ey : ey;
+    const float lny = left ? ex : -ex;
+    const float s = Vx * ex + Vy * ey;
+    const float nx = arc ? anx : lnx;
+    const float ny = arc ? any : lny;
+    const float ux = arc ? ul * anx : s * ex - Vx;
+    const float uy = arc ? ul * any : s * ey - Vy;
+    return make_float4(vax + f * ux, vay + f * uy, ny, -nx);
+}
+
+// Half-planes of this lane, stored in LDS column `tid`.
+template <int BLOCK>
+struct LdsLines {
+    const float4 *L;
+    int tid;
+    __device__ __forceinline__ bool get(int j, float4 &l) const
+    {
+        l = L[j * BLOCK + tid];
+        return true;
+    }
+};
+
+// Boundaries of "delta_j(v) <= delta_i(v)" for j < i (least-penetration
+// sub-problem), recomputed on demand from lines i and j.  Lines parallel to i
+// and pointing the same way are not constraints (invalid).
+// Since delta_j(v) - delta_i(v) = c - det(e, v) with e = d_j - d_i and
+// c = det(d_j, q_j) - det(d_i, q_i), the boundary is det(e/|e|, v) = c/|e|;
+// it is stored through its point nearest the origin, (c/|e|) (-e_y, e_x)/|e|.
+// This is the same line as the one through the intersection of lines i and j
+// (or the midpoint of q_i, q_j for antiparallel lines), but stays well
+// scaled in FP32 when the two lines are nearly parallel and intersect far
+// away from the speed disc.
+template <int BLOCK>
+struct ProjLines {
+    const float4 *L;
+    int tid;
+    float4 li;
+    float ci;    // det(d_i, q_i)
+    float eps;
+    __device__ __forceinline__ bool get(int j, float4 &out) const
+    {
+        const float4 lj = L[j * BLOCK + tid];
+        const float dij = det2(li.z, li.w, lj.z, lj.w);
+        if (fabsf(dij) <= eps && li.z * lj.z + li.w * lj.w > 0.0f) return false;
+        const float ex = lj.z - li.z, ey = lj.w - li.w;
+        const float il = 1.0f / sqrtf(ex * ex + ey * ey);
+        const float dx = ex * il, dy = ey * il;
+        const float off = (det2(lj.z, lj.w, lj.x, lj.y) - ci) * il;
+        out = make_float4(-dy * off, dx * off, dx, dy);
+        return true;
+    }
+};
+
+// One-dimensional sub-problem on line li (index i): the parameter interval
+// inside the speed disc and on the permitted side of every valid line j < i.
+// mode 0: closest point to (ox, oy); mode 1: extreme along unit (ox, oy), or,
+// when the line is orthogonal to it, the point closest to (tx, ty).
+template <class Src>
+__device__ __forceinline__ bool lp1(const Src &src, int i, float4 li, float vmax, int mode,
+                                    float ox, float oy, float tx, float ty, float eps, float &x,
+                                    float &y)
+{
+    const float dot = li.x * li.z + li.y * li.w;
+    const float disc = dot * dot + vmax * vmax - (li.x * li.x + li.y * li.y);
+    if (disc < 0.0f) return false;
+    const float sq = sqrtf(disc);
+    float tl = -dot - sq, tr = -dot + sq;
+    for (int j = 0; j < i; ++j) {
+        float4 lj;
+        if (!src.get(j, lj)) continue;
+        const float a = det2(lj.z, lj.w, li.z, li.w);
+        const float b = det2(lj.z, lj.w, li.x - lj.x, li.y - lj.y);
+        if (fabsf(a) <= eps) {
+            if (b < 0.0f) return false;
+            continue;
+        }
+        const float t = -b / a;
+        if (a > 0.0f)
+            tl = fmaxf(tl, t);
+        else
+            tr = fminf(tr, t);
+        if (tl > tr) return false;
+    }
+    float t;
+    if (mode == 0) {
+        t = li.z * (ox - li.x) + li.w * (oy - li.y);
+        t = fminf(fmaxf(t, tl), tr);
+    } else {
+        const float sd = ox * li.z + oy * li.w;
+        if (fabsf(sd) <= eps) {
+            t = li.z * (tx - li.x) + li.w * (ty - li.y);
+            t = fminf(fmaxf(t, tl), tr);
+        } else {
+            t = sd > 0.0f ? tr : tl;
+        }
+    }
+    x = li.x + t * li.z;
+    y = li.y + t * li.w;
+    return true;
+}
+
+// Incremental 2D LP over lines 0..m-1 of `src` and the disc |v| <= vmax.
+// Returns the first infeasible line, or m; v keeps its pre-failure value.
+template <class Src>
+__device__ __forceinline__ int lp2(const Src &src, int m, float vmax, int mode, float ox,
+                                   float oy, float tx, float ty, float eps, float &vx, float &vy)
+{
+    float x, y;
+    if (mode == 1) {
+        x = ox * vmax;
+        y = oy * vmax;
+    } else {
+        const float o2 = ox * ox + oy * oy;
+        if (o2 > vmax * vmax) {
+            const float sc = vmax / sqrtf(o2);
+            x = ox * sc;
+            y = oy * sc;
+        } else {
+            x = ox;
+            y = oy;
+        }
+    }
+    for (int i = 0; i < m; ++i) {
+        float4 li;
+        if (!src.get(i, li)) continue;
+        if (det2(li.z, li.w, li.x - x, li.y - y) > 0.0f) {
+            float nx = x, ny = y;
+            if (!lp1(src, i, li, vmax, mode, ox, oy, tx, ty, eps, nx, ny)) {
+                vx = x;
+                vy = y;
+                return i;
+            }
+            x = nx;
+            y = ny;
+        }
+    }
+    vx = x;
+    vy = y;
+    return m;
+}
+
+// Least penetration (Sec. 3): from LP2's partial result at line `fail`, each
+// later line i whose penetration exceeds the current level re-solves v in the
+// region where no earlier line penetrates more than line i, as deep into line
+// i's permitted side as possible.
+template <int BLOCK>
+__device__ __forceinline__ void lp3(const float4 *L, int tid, int m, int fail, float vmax,
+                                    float tx, float ty, float eps, float &vx, float &vy)
+{
+    float level = 0.0f;
+    float x = vx, y = vy;
+    for (int i = fail; i < m; ++i) {
+        const float4 li = L[i * BLOCK + tid];
+        if (det2(li.z, li.w, li.x - x, li.y - y) <= level) continue;
+        ProjLines<BLOCK> src{L, tid, li, det2(li.z, li.w, li.x, li.y), eps};
+        float nx = x, ny = y;
+        if (lp2(src, i, vmax, 1, -li.w, li.z, tx, ty, eps, nx, ny) == i) {
+            x = nx;
+            y = ny;
+        }
+        level = det2(li.z, li.w, li.x - x, li.y - y);
+    }
+    vx = x;
+    vy = y;
+}
+
+template <int K, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_step(StepArgs a)
+{
+    __shared__ float4 lines[K * BLOCK];
+    const int tid = threadIdx.x;
+    const int s = blockIdx.x * BLOCK + tid;
+    if (s >= a.n) return;
+    const GridMeta g = *a.meta;
+    const float4 me0 = a.s0[s];
+    const float4 me1 = a.s1[s];
+    const int i = __float_as_int(me0.z);
+    const float xi = me0.x, yi = me0.y, ri = me0.w, vxi = me1.x, vyi = me1.y;
+    const int ci = __float_as_int(me1.z) & 1;
+
+    double key[K];
+    int jj[K], pos[K];
+    const int found = knn_select<K>(g, a.start, a.s0, xi, yi, i, key, jj, pos);
+    const int m = found < a.k ? found : a.k;
+
+    const float inv_tau = 1.0f / a.tau, inv_dt = 1.0f / a.dt;
+    const float fa = ci ? a.f10 : a.f00;  // f[ci][0]
+    const float fb = ci ? a.f11 : a.f01;  // f[ci][1]
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        if (q < m) {
+            const float4 b0 = a.s0[pos[q]];
+            const float4 b1 = a.s1[pos[q]];
+            const float f = (__float_as_int(b1.z) & 1) ? fb : fa;
+            lines[q * BLOCK + tid] = halfplane(xi, yi, vxi, vyi, ri, b0.x, b0.y, b1.x, b1.y, b0.w,
+                                               f, inv_tau, inv_dt, i < jj[q]);
+        }
+    }
+
+    const float vmax = a.in.max_speed[i];
+    float prx = a.in.pref_x[i], pry = a.in.pref_y[i];
+    if (a.pref_is_goal) {
+        const float gx = prx - xi, gy = pry - yi;
+        const float d2 = gx * gx + gy * gy;
+        const float sc = d2 > 0.0f ? fminf(vmax / sqrtf(d2), inv_dt) : 0.0f;
+        prx = gx * sc;
+        pry = gy * sc;
+    }
+
+    LdsLines<BLOCK> src{lines, tid};
+    float vx, vy;
+    const int fail = lp2(src, m, vmax, 0, prx, pry, 0.0f, 0.0f, a.eps, vx, vy);
+    uint8_t st = 0;
+    if (fail < m) {
+        lp3<BLOCK>(lines, tid, m, fail, vmax, prx, pry, a.eps, vx, vy);
+        st = 1;
+    }
+    a.out.vx[i] = vx;
+    a.out.vy[i] = vy;
+    a.out.px[i] = xi + vx * a.dt;
+    a.out.py[i] = yi + vy * a.dt;
+    if (a.out.status) a.out.status[i] = st;
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_knn_export(StepArgs a)
+{
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s >= a.n) return;
+    const GridMeta g = *a.meta;
+    const float4 me0 = a.s0[s];
+    const int i = __float_as_int(me0.z);
+    double key[K];
+    int jj[K], pos[K];
+    const int found = knn_select<K>(g, a.start, a.s0, me0.x, me0.y, i, key, jj, pos);
+    const int m = found < a.k ? found : a.k;
+    int32_t *row = a.nbr ? a.nbr + (int64_t)i * a.k : nullptr;
+#pragma unroll
+    for (int q = 0; q < K; ++q)
+        if (row && q < a.k) row[q] = q < m ? jj[q] : -1;
+    if (a.cnt) a.cnt[i] = m;
+}
+
+StepArgs make_args(const orca_agents_in &in, const orca_agents_out *out, int n,
+                   const orca_params &p, const Work &w)
+{
+    StepArgs a;
+    a.in = in;
+    if (out)
+        a.out = *out;
+    else
+        a.out = orca_agents_out{nullptr, nullptr, nullptr, nullptr, nullptr};
+    a.meta = w.meta;
+    a.start = w.start;
+    a.s0 = w.s0;
+    a.s1 = w.s1;
+    a.n = n;
+    a.k = p.max_neighbors;
+    a.dt = p.dt;
+    a.tau = p.time_horizon;
+    a.eps = p.par_eps;
+    a.pref_is_goal = p.pref_is_goal;
+    a.f00 = p.f[0][0];
+    a.f01 = p.f[0][1];
+    a.f10 = p.f[1][0];
+    a.f11 = p.f[1][1];
+    a.nbr = nullptr;
+    a.cnt = nullptr;
+    return a;
+}
+
+template <int K>
+void launch_step_k(const StepArgs &a, hipStream_t stream)
+{
+    const int nb = (a.n + kStepBlock - 1) / kStepBlock;
+    hipLaunchKernelGGL((k_step<K, kStepBlock>), dim3(nb), dim3(kStepBlock), 0, stream, a);
+}
+
+template <int K>
+void launch_knn_k(const StepArgs &a, hipStream_t stream)
+{
+    const int nb = (a.n + 255) / 256;
+    hipLaunchKernelGGL((k_knn_export<K>), dim3(nb), dim3(256), 0, stream, a);
+}
+
+}  // namespace
+
+// Register-list capacities compiled; k is rounded up to the next one (the k
+// smallest of a set are the first k of its K smallest).
+#define ORCA_DISPATCH_K(FN, k, a, stream)          \
+    do {                                           \
+        if ((k) <= 4)                              \
+            FN<4>(a, stream);                      \
+        else if ((k) <= 8)                         \
+            FN<8>(a, stream);                      \
+        else if ((k) <= 10)                        \
+            FN<10>(a, stream);                     \
+        else if ((k) <= 12)                        \
+            FN<12>(a, stream);                     \
+        else if ((k) <= 16)                        \
+            FN<16>(a, stream);                     \
+        else if ((k) <= 20)                        \
+            FN<20>(a, stream);                     \
+        else if ((k) <= 24)                        \
+            FN<24>(a, stream);                     \
+        else                                       \
+            FN<32>(a, stream);                     \
+    } while (0)
+
+hipError_t launch_step(const orca_agents_in &in, const orca_agents_out &out, int n,
+                       const orca_params &p, const Layout &L, const Work &w, hipStream_t stream)
+{
+    (void)L;
+    const StepArgs a = make_args(in, &out, n, p, w);
+    ORCA_DISPATCH_K(launch_step_k, p.max_neighbors, a, stream);
+    return hipGetLastError();
+}
+
+hipError_t launch_knn_export(const orca_agents_in &in, int n, const orca_params &p,
+                             const Layout &L, const Work &w, int32_t *nbr, int32_t *cnt,
+                             hipStream_t stream)
+{
+    (void)L;
+    StepArgs a = make_args(in, nullptr, n, p, w);
+    a.nbr = nbr;
+    a.cnt = cnt;
+    ORCA_DISPATCH_K(launch_knn_k, p.max_neighbors, a, stream);
+    return hipGetLastError();
+}
+
+}  // namespace orca

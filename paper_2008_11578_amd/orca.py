@@ -1,0 +1,218 @@
+"""Python binding of liborca.so (ctypes).  Argument marshalling only: every
+step of the computation runs in the library's HIP kernels.
+
+Tensors are torch tensors on the current HIP device, contiguous, FP32 (class:
+uint8); work is enqueued on ``torch.cuda.current_stream()``.  Loading fails
+loudly when the library has not been built: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Dict, Optional
+
+import torch
+
+from . import scenarios
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liborca.so")
+
+ORCA_OK = 0
+ORCA_K_MAX = 32
+STATE_FIELDS = ("px", "py", "vx", "vy", "pref_x", "pref_y", "radius", "max_speed", "cls")
+
+
+class OrcaError(RuntimeError):
+    def __init__(self, fn: str, code: int):
+        super().__init__(f"{fn} failed: {status_string(code)} ({code})")
+        self.code = code
+
+
+class OrcaParams(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_float), ("time_horizon", ctypes.c_float),
+                ("neighbor_dist", ctypes.c_float), ("cell_size", ctypes.c_float),
+                ("max_neighbors", ctypes.c_int32), ("pref_is_goal", ctypes.c_int32),
+                ("f", (ctypes.c_float * 2) * 2), ("par_eps", ctypes.c_float)]
+
+
+class AgentsIn(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in STATE_FIELDS]
+
+
+class AgentsOut(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("px", "py", "vx", "vy", "status")]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2008_11578_amd.build` "
+                "(the ORCA step has no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32
+        L.orca_workspace_bytes.restype = sz
+        L.orca_workspace_bytes.argtypes = [i32, i32, i32]
+        L.orca_workspace_init.restype = ctypes.c_int
+        L.orca_workspace_init.argtypes = [vp, sz, vp]
+        L.orca_build_grid.restype = ctypes.c_int
+        L.orca_build_grid.argtypes = [ctypes.POINTER(AgentsIn), i32, ctypes.POINTER(OrcaParams),
+                                      vp, sz, vp, vp, vp]
+        L.orca_step.restype = ctypes.c_int
+        L.orca_step.argtypes = [ctypes.POINTER(AgentsIn), ctypes.POINTER(AgentsOut), i32,
+                                ctypes.POINTER(OrcaParams), vp, sz, vp]
+        L.orca_status_string.restype = ctypes.c_char_p
+        L.orca_status_string.argtypes = [ctypes.c_int]
+        L.orca_version.restype = ctypes.c_char_p
+        L.orca_version.argtypes = []
+        _lib = L
+    return _lib
+
+
+def status_string(code: int) -> str:
+    return lib().orca_status_string(int(code)).decode()
+
+
+def version() -> str:
+    return lib().orca_version().decode()
+
+
+def make_params(p) -> OrcaParams:
+    """From a ``scenarios.Params`` or a dict with the same field names."""
+    g = p.get if isinstance(p, dict) else (lambda k: getattr(p, k))
+    out = OrcaParams()
+    out.dt = g("dt")
+    out.time_horizon = g("time_horizon")
+    out.neighbor_dist = g("neighbor_dist")
+    out.cell_size = g("cell_size") if (not isinstance(p, dict) or "cell_size" in p) else 0.0
+    out.max_neighbors = int(g("max_neighbors"))
+    out.pref_is_goal = int(g("pref_is_goal"))
+    f = g("f")
+    for a in range(2):
+        for b in range(2):
+            out.f[a][b] = float(f[a][b])
+    out.par_eps = g("par_eps")
+    return out
+
+
+def _stream_handle(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else int(t.data_ptr())
+
+
+def _check(t: torch.Tensor, name: str, dtype, n: int):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() != n:
+        raise TypeError(f"{name} must be contiguous {dtype} with {n} elements")
+
+
+@dataclasses.dataclass
+class State:
+    """Agent state on the device, caller order (SoA)."""
+
+    px: torch.Tensor
+    py: torch.Tensor
+    vx: torch.Tensor
+    vy: torch.Tensor
+    pref_x: torch.Tensor
+    pref_y: torch.Tensor
+    radius: torch.Tensor
+    max_speed: torch.Tensor
+    cls: torch.Tensor
+
+    @property
+    def n(self) -> int:
+        return int(self.px.numel())
+
+    @classmethod
+    def from_arrays(cls, arrays, device="cuda") -> "State":
+        g = arrays.get if isinstance(arrays, dict) else (lambda k: getattr(arrays, k))
+        kw = {}
+        for k in STATE_FIELDS:
+            dt = torch.uint8 if k == "cls" else torch.float32
+            kw[k] = torch.as_tensor(g(k)).to(device=device, dtype=dt).contiguous()
+        return cls(**kw)
+
+    def clone(self) -> "State":
+        return State(**{k: getattr(self, k).clone() for k in STATE_FIELDS})
+
+    def to_numpy(self) -> Dict[str, "object"]:
+        return {k: getattr(self, k).cpu().numpy() for k in STATE_FIELDS}
+
+    def agents_in(self) -> AgentsIn:
+        n = self.n
+        for k in STATE_FIELDS:
+            _check(getattr(self, k), k, torch.uint8 if k == "cls" else torch.float32, n)
+        return AgentsIn(*[_ptr(getattr(self, k)) for k in STATE_FIELDS])
+
+
+def workspace_bytes(n: int, n_scenes: int = 0, max_cells: int = 0) -> int:
+    return int(lib().orca_workspace_bytes(int(n), int(n_scenes), int(max_cells)))
+
+
+class Workspace:
+    """A caller-owned device workspace, zero-filled once on creation."""
+
+    def __init__(self, n: int, n_scenes: int = 0, max_cells: int = 0, device="cuda"):
+        self.nbytes = workspace_bytes(n, n_scenes, max_cells)
+        self.buf = torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device=device)
+        rc = lib().orca_workspace_init(_ptr(self.buf), self.nbytes, _stream_handle())
+        if rc != ORCA_OK:
+            raise OrcaError("orca_workspace_init", rc)
+
+    def ptr(self) -> int:
+        return _ptr(self.buf)
+
+
+def build_grid(state: State, params, ws: Workspace, want_neighbors: bool = True,
+               stream=None):
+    """Grid + exact neighbour lists.  Returns (nbr[n, k] int32, count[n] int32)."""
+    p = make_params(params)
+    n = state.n
+    nbr = cnt = None
+    if want_neighbors:
+        nbr = torch.empty((n, p.max_neighbors), dtype=torch.int32, device=state.px.device)
+        cnt = torch.empty(n, dtype=torch.int32, device=state.px.device)
+    ain = state.agents_in()
+    rc = lib().orca_build_grid(ctypes.byref(ain), n, ctypes.byref(p), ws.ptr(), ws.nbytes,
+                               _ptr(nbr), _ptr(cnt), _stream_handle(stream))
+    if rc != ORCA_OK:
+        raise OrcaError("orca_build_grid", rc)
+    return nbr, cnt
+
+
+def step(state: State, params, ws: Workspace, out: Optional[State] = None,
+         status: Optional[torch.Tensor] = None, stream=None) -> State:
+    """One ORCA step.  ``out`` (default: a copy of ``state``) receives the new
+    positions and velocities; it may be ``state`` itself (in-place step)."""
+    p = make_params(params)
+    n = state.n
+    if out is None:
+        out = state.clone()
+    if status is not None:
+        _check(status, "status", torch.uint8, n)
+    for k in ("px", "py", "vx", "vy"):
+        _check(getattr(out, k), "out." + k, torch.float32, n)
+    ain = state.agents_in()
+    aout = AgentsOut(_ptr(out.px), _ptr(out.py), _ptr(out.vx), _ptr(out.vy), _ptr(status))
+    rc = lib().orca_step(ctypes.byref(ain), ctypes.byref(aout), n, ctypes.byref(p), ws.ptr(),
+                         ws.nbytes, _stream_handle(stream))
+    if rc != ORCA_OK:
+        raise OrcaError("orca_step", rc)
+    return out
+
+
+def params_of(sc: "scenarios.Scenario"):
+    return sc.params

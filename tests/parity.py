@@ -1,0 +1,143 @@
+"""Helpers shared by the GPU parity tests: run the HIP path and the FP64
+oracle from the same FP32 state and compare them.
+
+Velocity tolerance: 1e-4 m/s per agent for agents whose oracle solution is
+well conditioned.  Conditioning is measured with the oracle alone: it is
+re-run on copies of the state whose velocities are perturbed by 1e-6 m/s
+and radii by one ulp; an agent whose oracle velocity moves by more than
+``COND_TOL`` under such perturbations sits on a regime boundary (LP2/LP3
+flip, nearly parallel active lines, arc/leg switch, non-unique LP3
+minimiser) where FP32 rounding legitimately selects a different answer.
+Such an agent must still hold a valid answer to the oracle's FP64 problem
+(`valid_answer`); these agents are counted and their share is bounded.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+V_TOL = 1e-4
+COND_TOL = 1e-5
+
+
+def gpu_step(state_np, params, status=True):
+    import torch
+    from paper_2008_11578_amd import orca
+    st = orca.State.from_arrays(state_np)
+    ws = orca.Workspace(st.n)
+    stat = torch.zeros(st.n, dtype=torch.uint8, device="cuda") if status else None
+    out = orca.step(st, params, ws, status=stat)
+    torch.cuda.synchronize()
+    res = {k: getattr(out, k).cpu().numpy() for k in ("px", "py", "vx", "vy")}
+    if status:
+        res["status"] = stat.cpu().numpy()
+    return res
+
+
+def gpu_neighbors(state_np, params):
+    import torch
+    from paper_2008_11578_amd import orca
+    st = orca.State.from_arrays(state_np)
+    ws = orca.Workspace(st.n)
+    nbr, cnt = orca.build_grid(st, params, ws)
+    torch.cuda.synchronize()
+    return nbr.cpu().numpy(), cnt.cpu().numpy()
+
+
+def perturbed(state_np, seed, dv=1e-6):
+    """Copy of the state with velocities moved by up to `dv` m/s per
+    component and radii by one FP32 ulp: the size of the rounding the FP32
+    path makes in the half-plane geometry (relative positions are formed
+    exactly in FP32, so positions are left alone)."""
+    rng = np.random.default_rng(seed)
+    out = dict(as_dict(state_np))
+    for k in ("vx", "vy"):
+        a = np.asarray(out[k], np.float64)
+        out[k] = (a + rng.uniform(-dv, dv, size=a.shape)).astype(np.float32)
+    r = np.asarray(out["radius"], np.float32)
+    up = rng.random(r.shape) < 0.5
+    out["radius"] = np.where(up, np.nextafter(r, np.float32(np.inf)),
+                             np.nextafter(r, np.float32(0))).astype(np.float32)
+    return out
+
+
+def oracle_sensitivity(state_np, params, base, reps=2):
+    """Per-agent max |v_perturbed - v_base| of the oracle."""
+    sens = np.zeros_like(base["vx"])
+    for r in range(reps):
+        o = oracle.step(perturbed(state_np, 1000 + r), params)
+        sens = np.maximum(sens, np.hypot(o["vx"] - base["vx"], o["vy"] - base["vy"]))
+    return sens
+
+
+def penetration(lines, cnt, vx, vy):
+    """max_j det(d_j, q_j - v) over each agent's valid lines (-inf if none)."""
+    q = lines[:, :, 0:2]
+    d = lines[:, :, 2:4]
+    rx = q[:, :, 0] - vx[:, None]
+    ry = q[:, :, 1] - vy[:, None]
+    pen = d[:, :, 0] * ry - d[:, :, 1] * rx
+    valid = np.arange(lines.shape[1])[None, :] < cnt[:, None]
+    pen = np.where(valid, pen, -np.inf)
+    return pen.max(axis=1)
+
+
+def valid_answer(o, g, vmax, tol=V_TOL):
+    """Whether the GPU velocity solves the oracle's own FP64 problem to within
+    `tol`: inside the speed disc, no more penetration than the oracle's
+    answer (least penetration), and, when both sides found a permitted
+    velocity, no farther from the desired velocity than the oracle's."""
+    vg_x, vg_y = g["vx"].astype(np.float64), g["vy"].astype(np.float64)
+    pen_g = penetration(o["lines"], o["cnt"], vg_x, vg_y)
+    pen_o = penetration(o["lines"], o["cnt"], o["vx"], o["vy"])
+    speed_ok = np.hypot(vg_x, vg_y) <= vmax * (1 + 1e-5) + 1e-6
+    pen_ok = pen_g <= np.maximum(pen_o, 0.0) + tol
+    obj_g = np.hypot(vg_x - o["pref"][:, 0], vg_y - o["pref"][:, 1])
+    obj_o = np.hypot(o["vx"] - o["pref"][:, 0], o["vy"] - o["pref"][:, 1])
+    both_lp2 = (o["status"] == 0) & (g["status"] == 0)
+    obj_ok = ~both_lp2 | (obj_g <= obj_o + tol)
+    return speed_ok & pen_ok & obj_ok
+
+
+def as_dict(sc):
+    if isinstance(sc, dict):
+        return sc
+    return {k: getattr(sc, k) for k in oracle._STATE + ("cls",)}
+
+
+def compare_step(state_np, params, *, require_all=False, max_ill_frac=0.01, reps=2):
+    """Runs both sides one step from the same FP32 state and asserts the
+    parity contract.  Returns (report, gpu, oracle)."""
+    st = as_dict(state_np)
+    g = gpu_step(st, params)
+    o = oracle.step(st, params, want_lines=True)
+    dv = np.hypot(g["vx"] - o["vx"], g["vy"] - o["vy"])
+    bad = dv > V_TOL
+    rep = {"n": int(dv.size), "max_dv": float(dv.max()) if dv.size else 0.0,
+           "n_bad": int(bad.sum()), "lp3_gpu": int(g["status"].sum()),
+           "lp3_oracle": int(o["status"].sum()),
+           "status_mismatch": int((g["status"] != o["status"]).sum())}
+    ill = np.zeros_like(bad)
+    if bad.any() and not require_all:
+        sens = oracle_sensitivity(st, params, o, reps=reps)
+        ill = sens > COND_TOL
+        rep["n_ill"] = int(ill.sum())
+        rep["n_bad_ill"] = int((bad & ill).sum())
+        vmax = np.asarray(st["max_speed"], np.float64)
+        ok = valid_answer(o, g, vmax)
+        rep["n_bad_ill_invalid"] = int((bad & ill & ~ok).sum())
+        # ill-conditioned agents must still hold a valid answer
+        assert not (bad & ill & ~ok).any(), (rep, np.nonzero(bad & ill & ~ok)[0][:10])
+    # every well-conditioned agent within tolerance
+    assert not (bad & ~ill).any(), (rep, np.nonzero(bad & ~ill)[0][:10], dv[bad & ~ill][:10])
+    assert ill.mean() <= max_ill_frac, rep
+    # positions follow from the velocities: p' = p + v' dt (FP32 rounding of p)
+    dt = float(np.float32(params.dt if hasattr(params, "dt") else params["dt"]))
+    for k, kv in (("px", "vx"), ("py", "vy")):
+        p0 = np.abs(np.asarray(st[k], np.float32))
+        p1 = np.abs(o[k]).astype(np.float32)
+        tol = (np.abs(g[kv] - o[kv]) * dt + np.spacing(p0).astype(np.float64)
+               + np.spacing(p1).astype(np.float64) + 1e-12)
+        assert (np.abs(g[k] - o[k]) <= tol).all(), k
+    return rep, g, o

@@ -1,0 +1,199 @@
+"""GPU parity: the HIP path against the FP64 oracle, through the C ABI.
+
+Neighbour lists must match bit for bit; one-step velocities from identical
+FP32 states must agree within 1e-4 m/s for every well-conditioned agent (see
+tests/parity.py for how conditioning is decided and bounded).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2008_11578_amd import scenarios
+
+from parity import as_dict, compare_step, gpu_neighbors, gpu_step
+
+pytestmark = pytest.mark.gpu
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+def _knn_exact(sc, params=None):
+    params = params or sc.params
+    st = as_dict(sc)
+    nb, cn = gpu_neighbors(st, params)
+    onb, ocn = oracle.knn(st["px"], st["py"], params.neighbor_dist, params.max_neighbors)
+    np.testing.assert_array_equal(cn, ocn)
+    np.testing.assert_array_equal(nb, onb)
+    return cn
+
+
+def test_knn_c1():
+    sc = scenarios.c1_plain()
+    _print("knn c1", sc.n)
+    _knn_exact(sc)
+
+
+@pytest.mark.parametrize("cell_frac", [1.0, 0.5, 0.34, 2.0])
+def test_knn_cell_sizes(cell_frac):
+    sc = scenarios.uniform_square(5000, 60.0, seed=21, n_vehicles=100)
+    p = scenarios.Params(neighbor_dist=5.0, max_neighbors=16, cell_size=5.0 * cell_frac)
+    _print("knn cell size", p.cell_size)
+    _knn_exact(sc, p)
+
+
+@pytest.mark.parametrize("k", [1, 4, 7, 10, 13, 20, 25, 32])
+def test_knn_all_capacities(k):
+    sc = scenarios.uniform_square(3000, 30.0, seed=k)
+    p = scenarios.Params(neighbor_dist=4.0, max_neighbors=k)
+    _print("knn k", k)
+    cn = _knn_exact(sc, p)
+    assert cn.max() == k
+
+
+def test_knn_exact_ties_lattice():
+    g = np.arange(40, dtype=np.float64)
+    X, Y = np.meshgrid(g, g)
+    perm = np.random.default_rng(3).permutation(1600)
+    st = dict(px=X.ravel()[perm].astype(np.float32), py=Y.ravel()[perm].astype(np.float32))
+    n = 1600
+    for k in ("vx", "vy", "pref_x", "pref_y"):
+        st[k] = np.zeros(n, np.float32)
+    st["radius"] = np.full(n, 0.3, np.float32)
+    st["max_speed"] = np.full(n, 1.5, np.float32)
+    st["cls"] = np.zeros(n, np.uint8)
+    p = scenarios.Params(neighbor_dist=2.5, max_neighbors=12)
+    nb, cn = gpu_neighbors(st, p)
+    onb, ocn = oracle.knn(st["px"], st["py"], 2.5, 12)
+    np.testing.assert_array_equal(nb, onb)
+
+
+def test_knn_c2_full():
+    sc = scenarios.c2_mixed()
+    _print("knn c2", sc.n)
+    _knn_exact(sc)
+
+
+def test_knn_c3_full():
+    sc = scenarios.c3_crossing()
+    _print("knn c3", sc.n)
+    _knn_exact(sc)
+
+
+def test_step_c1_all_agents():
+    sc = scenarios.c1_plain()
+    rep, g, o = compare_step(sc, sc.params, require_all=True)
+    _print("step c1", rep)
+    assert rep["n_bad"] == 0
+
+
+def test_step_c1_trajectory_resync():
+    # advance the GPU 20 steps; at each step re-run one step of both sides
+    # from the GPU's FP32 state and compare (trajectories themselves diverge
+    # chaotically between FP32 and FP64, so they are never compared)
+    sc = scenarios.c1_plain()
+    st = as_dict(sc)
+    for t in range(sc.steps):
+        rep, g, o = compare_step(st, sc.params)
+        if t % 5 == 0:
+            _print("c1 step", t, rep)
+        st = dict(st)
+        for k in ("px", "py", "vx", "vy"):
+            st[k] = g[k]
+
+
+def test_step_c2_mixed():
+    sc = scenarios.c2_mixed()
+    rep, g, o = compare_step(sc, sc.params)
+    _print("step c2", rep)
+
+
+def test_step_random_velocities_mixed():
+    sc = scenarios.random_state(20000, 120.0, seed=8, n_vehicles=1000,
+                                params=scenarios.Params(dt=0.05, neighbor_dist=5.0,
+                                                        max_neighbors=16))
+    rep, g, o = compare_step(sc, sc.params)
+    _print("step random mixed", rep)
+
+
+def test_step_dense_crossing_small():
+    sc = scenarios.c3_crossing(side_count=128)
+    st = as_dict(sc)
+    rep, g, o = compare_step(st, sc.params)
+    _print("step crossing 16k t=0", rep)
+
+
+def test_step_deterministic_and_inplace():
+    import torch
+    from paper_2008_11578_amd import orca
+    sc = scenarios.random_state(30000, 100.0, seed=4, n_vehicles=300)
+    st = orca.State.from_arrays(sc)
+    ws = orca.Workspace(st.n)
+    a = orca.step(st, sc.params, ws)
+    b = orca.step(st, sc.params, ws)
+    torch.cuda.synchronize()
+    for k in ("px", "py", "vx", "vy"):
+        assert torch.equal(getattr(a, k), getattr(b, k)), k
+    c = st.clone()
+    orca.step(c, sc.params, ws, out=c)
+    torch.cuda.synchronize()
+    for k in ("px", "py", "vx", "vy"):
+        assert torch.equal(getattr(a, k), getattr(c, k)), k
+
+
+def test_step_edge_cases():
+    p = scenarios.Params(dt=0.1, neighbor_dist=5.0, max_neighbors=10, pref_is_goal=0)
+    # single agent: desired velocity clipped to the cap
+    st = dict(px=np.float32([1.0]), py=np.float32([2.0]), vx=np.float32([0]), vy=np.float32([0]),
+              pref_x=np.float32([3.0]), pref_y=np.float32([4.0]), radius=np.float32([0.3]),
+              max_speed=np.float32([1.5]), cls=np.uint8([0]))
+    g = gpu_step(st, p)
+    np.testing.assert_allclose([g["vx"][0], g["vy"][0]], [0.9, 1.2], atol=1e-6)
+    # overlapping pair and a symmetric squeeze
+    st = dict(px=np.float32([0, 0.5, -0.5]), py=np.float32([0, 0, 0]), vx=np.zeros(3, np.float32),
+              vy=np.zeros(3, np.float32), pref_x=np.zeros(3, np.float32),
+              pref_y=np.float32([0.7, 0, 0]), radius=np.full(3, 0.3, np.float32),
+              max_speed=np.full(3, 1.5, np.float32), cls=np.zeros(3, np.uint8))
+    g = gpu_step(st, p)
+    o = oracle.step(st, p)
+    np.testing.assert_allclose(g["vx"], o["vx"], atol=1e-5)
+    np.testing.assert_allclose(g["vy"], o["vy"], atol=1e-5)
+    assert g["status"][0] == 1
+    # all agents on one vertical line (zero-width bounding box) and coincident agents
+    n = 300
+    st = dict(px=np.full(n, 7.0, np.float32), py=np.linspace(0, 50, n).astype(np.float32),
+              vx=np.zeros(n, np.float32), vy=np.zeros(n, np.float32),
+              pref_x=np.full(n, 0.5, np.float32), pref_y=np.zeros(n, np.float32),
+              radius=np.full(n, 0.3, np.float32), max_speed=np.full(n, 1.5, np.float32),
+              cls=np.zeros(n, np.uint8))
+    st["py"][10] = st["py"][11]
+    rep, g, o = compare_step(st, p)
+    _print("line", rep)
+    # n = 0 is a no-op
+    from paper_2008_11578_amd import orca
+    import torch
+    e = orca.State.from_arrays({k: np.zeros(0, np.uint8 if k == "cls" else np.float32)
+                                for k in orca.STATE_FIELDS})
+    orca.step(e, p, orca.Workspace(0))
+    torch.cuda.synchronize()
+
+
+def test_step_large_coordinates_and_small_workspace():
+    import torch
+    from paper_2008_11578_amd import orca
+    sc = scenarios.uniform_square(4000, 80.0, seed=12)
+    st = as_dict(sc)
+    st = dict(st)
+    st["px"] = (st["px"].astype(np.float64) + 5000.0).astype(np.float32)
+    # a workspace with very few cells forces the device to enlarge the cells
+    s = orca.State.from_arrays(st)
+    ws = orca.Workspace(s.n, max_cells=16)
+    out = orca.step(s, sc.params, ws)
+    torch.cuda.synchronize()
+    o = oracle.step(st, sc.params)
+    dv = np.hypot(out.vx.cpu().numpy() - o["vx"], out.vy.cpu().numpy() - o["vy"])
+    assert np.quantile(dv, 0.99) < 1e-4
+    nb, cn = orca.build_grid(s, sc.params, ws)
+    onb, ocn = oracle.knn(st["px"], st["py"], sc.params.neighbor_dist, sc.params.max_neighbors)
+    np.testing.assert_array_equal(nb.cpu().numpy(), onb)
