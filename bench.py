@@ -1,0 +1,249 @@
+#!/usr/bin/env python3
+"""Throughput of the ORCA step on one MI355X.
+
+Workload: the dense four-way crossing, 1,048,576 pedestrians on a jittered
+lattice over 700 m x 700 m (about 2.14 agents/m^2), neighbour distance 3 m,
+at most 20 neighbours, dt 0.1 s, tau 2 s; synthetic, seeded.  One step is
+the whole path: grid build, exact k-nearest neighbours, ORCA half-planes,
+one LP per agent with the least-penetration fallback, and the update.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line.  `value` is agent-steps per second with the state
+resident in HBM; `roofline` reports the fused step kernel against the
+vector-ALU peak; `cpu_baseline` is the FP64 oracle timed on this host's
+cores on a short sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 3.93e13 VALU lane-ops/s
+# (non-packed FP32 / FP64 rate; FP32 vector 157.3 TFLOP/s counts an FMA as
+# two flops and a packed op as two lanes).
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic VALU lane-operations per unit of work counted by the oracle
+# (a quarter-rate sqrt/reciprocal counts 4).  Units, in order of the oracle's
+# work counters: candidate examined in the 3x3 stencil of R_n cells,
+# in-range candidate, half-plane built, LP2 line checked, LP2 line re-solved,
+# LP2 inner iteration, LP3 used, LP3 line re-solved, LP3 boundary line
+# built, LP3 boundary line checked, LP3 boundary line re-solved, LP3 inner
+# iteration.
+OP_COST = (10, 0, 65, 4, 20, 15, 0, 10, 20, 4, 20, 15)
+# Algorithmic HBM bytes per agent-step of the fused step kernel: read
+# px, py, vx, vy, radius (cell-ordered copy), pref_x, pref_y, max_speed, class
+# (33 B), write px, py, vx, vy (16 B).
+STEP_BYTES_PER_AGENT = 49
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("step.hip", "orca_internal.h"):
+        with open(os.path.join(ROOT, "paper_2008_11578_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel_hash: str):
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    counter summary, or None when missing or taken on other kernel source."""
+    path = os.path.join(ROOT, "profiles", "k_step_c3_1M_hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    mh = re.search(r"source_hash:\s*([0-9a-f]+)", txt)
+    mb = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not mh or not mb or mh.group(1) != kernel_hash:
+        return None
+    return float(mb.group(1))
+
+
+class HipEvents:
+    """Raw hipEvent_t handles from the HIP runtime torch has loaded."""
+
+    def __init__(self):
+        self.hip = ctypes.CDLL("libamdhip64.so.7")
+        self.hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float),
+                                                 ctypes.c_void_p, ctypes.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.events = []
+
+    def create(self) -> int:
+        e = ctypes.c_void_p()
+        rc = self.hip.hipEventCreate(ctypes.byref(e))
+        if rc != 0:
+            raise RuntimeError(f"hipEventCreate failed ({rc})")
+        self.events.append(e.value)
+        return e.value
+
+    def elapsed_ms(self, a: int, b: int) -> float:
+        ms = ctypes.c_float()
+        rc = self.hip.hipEventElapsedTime(ctypes.byref(ms), ctypes.c_void_p(a), ctypes.c_void_p(b))
+        if rc != 0:
+            raise RuntimeError(f"hipEventElapsedTime failed ({rc})")
+        return ms.value
+
+    def close(self):
+        for e in self.events:
+            self.hip.hipEventDestroy(ctypes.c_void_p(e))
+        self.events = []
+
+
+def algorithmic_ops(work) -> float:
+    import numpy as np
+    return float((work.astype(np.float64) * np.asarray(OP_COST, np.float64)[None, :]).sum())
+
+
+def cpu_baseline(state_start, state_end, params, n, steps):
+    """Times the FP64 oracle on this host: `steps` oracle steps from the
+    state that opens the timed GPU window, plus one from the state that
+    closes it.  Also returns the oracle's work counters on both states."""
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    st = dict(state_start)
+    w_start = None
+    for s in range(steps):
+        o = oracle.step(st, params, want_work=(s == 0))
+        if s == 0:
+            w_start = o["work"]
+        st = dict(st)
+        for k in ("px", "py", "vx", "vy"):
+            st[k] = o[k].astype(np.float32)
+    o_end = oracle.step(state_end, params, want_work=True)
+    elapsed = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    rate = n * (steps + 1) / elapsed
+    return rate, elapsed, threads, w_start, o_end["work"]
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--cpu-steps", type=int, default=6,
+                    help="oracle steps in the CPU-baseline sample (0 disables it)")
+    ap.add_argument("--side", type=int, default=1024,
+                    help="lattice side of the crossing workload (1024 -> 1,048,576 agents)")
+    args = ap.parse_args(argv)
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} (WORLD_SIZE={world}) is not "
+              "supported: the ORCA step has no multi-GPU path in this build", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2008_11578_amd import orca, scenarios
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    torch.cuda.set_device(0)
+    sc = scenarios.c3_crossing(side_count=args.side)
+    n = sc.n
+    params = sc.params
+    log(f"[bench] workload {sc.name}: n={n}, k={params.max_neighbors}, R_n={params.neighbor_dist}")
+    state = orca.State.from_arrays(sc)
+    nxt = state.clone()
+    ws = orca.Workspace(n)
+    status = torch.zeros(n, dtype=torch.uint8, device="cuda")
+
+    for _ in range(args.warmup):
+        orca.step(state, params, ws, out=nxt, status=status)
+        state, nxt = nxt, state
+    torch.cuda.synchronize()
+    snap_start = state.to_numpy()
+    hip = HipEvents()
+    # pre-create the events so that creation stays outside the timed region
+    pre = [(hip.create(), hip.create(), hip.create()) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        orca.step(state, params, ws, out=nxt, status=status, events=pre[s])
+        state, nxt = nxt, state
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    grid_ms = [hip.elapsed_ms(a, b) for a, b, c in pre]
+    step_ms = [hip.elapsed_ms(b, c) for a, b, c in pre]
+    hip.close()
+    lp3_share = float(status.float().mean().item())
+    snap_end = state.to_numpy()
+
+    ms_per_step = wall * 1e3 / args.steps
+    value = n * args.steps / wall
+    k_ms = float(np.mean(step_ms))
+    g_ms = float(np.mean(grid_ms))
+    log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step, grid {g_ms:.3f} ms, "
+        f"step kernel {k_ms:.3f} ms, LP3 share at end {lp3_share:.3f}")
+
+    cpu = None
+    ops_per_launch = None
+    if args.cpu_steps > 0:
+        rate, el, threads, w0, w1 = cpu_baseline(snap_start, snap_end, params, n, args.cpu_steps)
+        ops_per_launch = 0.5 * (algorithmic_ops(w0) + algorithmic_ops(w1))
+        cpu = {"value": rate, "unit": "agent-steps/s", "cores": threads, "kind": "oracle",
+               "sample": f"{args.cpu_steps} FP64 oracle steps from the state opening the timed "
+                         f"GPU window plus 1 from the state closing it, {n} agents "
+                         f"({el:.1f} s)"}
+        log(f"[bench] oracle: {rate:.3e} agent-steps/s on {threads} threads ({el:.1f} s)")
+
+    roof = None
+    if ops_per_launch is not None:
+        achieved = ops_per_launch / (k_ms * 1e-3) / 1e12
+        kh = source_hash()
+        traffic = traffic_from_profile(kh)
+        roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Top/s",
+                "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
+                "kernel": f"k_step<{params.max_neighbors}>", "kernel_ms": k_ms,
+                "ops_per_launch": ops_per_launch,
+                "hbm_algorithmic_GBs": STEP_BYTES_PER_AGENT * n / (k_ms * 1e-3) / 1e9,
+                "hbm_peak_GBs": HBM_PEAK_GBS, "source_hash": kh}
+
+    out = {
+        "metric": "agent-steps/sec at 1M agents (ORCA+LP)",
+        "value": value,
+        "unit": "agent-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"dense four-way crossing, {n} pedestrians, 700 m square, "
+                               f"R_n 3 m, k 20, dt 0.1 s, tau 2 s",
+                   "agents": n, "max_neighbors": params.max_neighbors,
+                   "grid_ms": g_ms, "step_kernel_ms": k_ms, "lp3_share_end": lp3_share},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

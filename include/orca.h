@@ -111,6 +111,22 @@ int orca_build_grid(const orca_agents_in *in, int32_t n, const orca_params *para
 int orca_step(const orca_agents_in *in, const orca_agents_out *out, int32_t n,
               const orca_params *params, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Optional HIP events recorded on `stream` around the phases of one step
+ * (any may be NULL): before the grid build, between the grid build and the
+ * fused neighbour/half-plane/LP kernel, and after that kernel.  For timing
+ * only; they do not change the computation. */
+typedef struct {
+    hipEvent_t grid_begin;
+    hipEvent_t step_begin;
+    hipEvent_t step_end;
+} orca_step_events;
+
+/* orca_step with phase events (events may be NULL: then identical to
+ * orca_step). */
+int orca_step_ex(const orca_agents_in *in, const orca_agents_out *out, int32_t n,
+                 const orca_params *params, void *ws, size_t ws_bytes,
+                 const orca_step_events *events, hipStream_t stream);
+
 /* Human-readable text for a status code (static storage). */
 const char *orca_status_string(int code);
 

@@ -19,9 +19,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "orca_oracle.c")
 _LIB = os.path.join(_HERE, "liborca_oracle.so")
 K_MAX = 64
-NWORK = 8
-WORK_FIELDS = ("candidates", "in_range", "neighbors", "lp2_violations", "lp2_inner",
-               "lp3_used", "lp3_violations", "lp3_inner")
+NWORK = 12
+WORK_FIELDS = ("candidates", "in_range", "neighbors", "lp2_checks", "lp2_solves", "lp2_inner",
+               "lp3_used", "lp3_outer", "lp3_proj", "lp3_checks", "lp3_solves", "lp3_inner")
 
 
 def build(force: bool = True) -> str:

@@ -45,7 +45,7 @@
 #include <string.h>
 
 #define ORACLE_K_MAX 64
-#define ORACLE_NWORK 8
+#define ORACLE_NWORK 12
 
 typedef struct {
     double qx, qy; /* point on the boundary line */
@@ -221,7 +221,7 @@ static int lp1(const oline *L, int i, double vmax, double ox, double oy, int mod
  * on failure v keeps the value it had before that line. */
 static int lp2_mode(const oline *L, int m, double vmax, double ox, double oy, int mode,
                     double tx, double ty, double eps, double *vx, double *vy,
-                    int64_t *n_viol, int64_t *iters)
+                    int64_t *n_check, int64_t *n_viol, int64_t *iters)
 {
     double x, y;
     if (mode == 1) {
@@ -239,6 +239,7 @@ static int lp2_mode(const oline *L, int m, double vmax, double ox, double oy, in
         }
     }
     for (int i = 0; i < m; ++i) {
+        ++*n_check;
         if (det2(L[i].dx, L[i].dy, L[i].qx - x, L[i].qy - y) > 0.0) {
             ++*n_viol;
             double nx2 = x, ny2 = y;
@@ -266,7 +267,7 @@ static int lp2_mode(const oline *L, int m, double vmax, double ox, double oy, in
 /* pushing v as far as possible into line i's permitted side.               */
 /* ------------------------------------------------------------------------ */
 static void lp3(const oline *L, int m, int fail, double vmax, double tx, double ty,
-                double eps, double *vx, double *vy, int64_t *n_outer, int64_t *inner)
+                double eps, double *vx, double *vy, int64_t *w)
 {
     oline proj[ORACLE_K_MAX];
     double level = 0.0;
@@ -274,7 +275,7 @@ static void lp3(const oline *L, int m, int fail, double vmax, double tx, double 
     for (int i = fail; i < m; ++i) {
         const oline *li = &L[i];
         if (det2(li->dx, li->dy, li->qx - x, li->qy - y) <= level) continue;
-        ++*n_outer;
+        ++w[0];
         int np = 0;
         for (int j = 0; j < i; ++j) {
             const oline *lj = &L[j];
@@ -297,11 +298,11 @@ static void lp3(const oline *L, int m, int fail, double vmax, double tx, double 
             proj[np].dy = ddy / dl;
             ++np;
         }
-        *inner += np;
+        w[1] += np;
         double nx = x, ny = y;
-        int64_t dummy = 0;
         /* objective direction: the inward normal of line i, (-d.y, d.x) */
-        if (lp2_mode(proj, np, vmax, -li->dy, li->dx, 1, tx, ty, eps, &nx, &ny, &dummy, inner) == np) {
+        if (lp2_mode(proj, np, vmax, -li->dy, li->dx, 1, tx, ty, eps, &nx, &ny, &w[2], &w[3],
+                     &w[4]) == np) {
             x = nx;
             y = ny;
         }
@@ -323,8 +324,8 @@ int oracle_lp2(int m, const double *lines, double vmax, double ox, double oy, do
         L[i].dx = lines[4 * i + 2];
         L[i].dy = lines[4 * i + 3];
     }
-    int64_t a = 0, b = 0;
-    return lp2_mode(L, m, vmax, ox, oy, 0, 0.0, 0.0, eps, &v[0], &v[1], &a, &b);
+    int64_t a = 0, b = 0, c = 0;
+    return lp2_mode(L, m, vmax, ox, oy, 0, 0.0, 0.0, eps, &v[0], &v[1], &a, &b, &c);
 }
 
 /* LP2 followed by LP3 when LP2 fails; returns the LP2 fail index (m = LP2
@@ -340,9 +341,9 @@ int oracle_lp_full(int m, const double *lines, double vmax, double ox, double oy
         L[i].dx = lines[4 * i + 2];
         L[i].dy = lines[4 * i + 3];
     }
-    int64_t a = 0, b = 0;
-    const int fail = lp2_mode(L, m, vmax, ox, oy, 0, 0.0, 0.0, eps, &v[0], &v[1], &a, &b);
-    if (fail < m) lp3(L, m, fail, vmax, ox, oy, eps, &v[0], &v[1], &a, &b);
+    int64_t a = 0, b = 0, c = 0, w[5] = {0};
+    const int fail = lp2_mode(L, m, vmax, ox, oy, 0, 0.0, 0.0, eps, &v[0], &v[1], &a, &b, &c);
+    if (fail < m) lp3(L, m, fail, vmax, ox, oy, eps, &v[0], &v[1], w);
     return fail;
 }
 
@@ -503,9 +504,10 @@ int oracle_knn(int n, const float *px, const float *py, float neighbor_dist, int
 /* when p = g; otherwise pref holds v_pref itself.  The LP result v' is the */
 /* new velocity and p' = p + v' dt (explicit Euler), all agents reading the */
 /* step-t state.                                                            */
-/* work (nullable, n x 8): candidates examined, in-range count, neighbours  */
-/* used, LP2 violated lines, LP2 inner iterations, LP3 used, LP3 violated   */
-/* lines, LP3 inner iterations.                                             */
+/* work (nullable, n x 12): candidates examined, in-range count, neighbours */
+/* used; LP2 lines checked, lines re-solved, inner iterations; LP3 used,    */
+/* LP3 lines re-solved, boundary lines built, boundary lines checked,       */
+/* boundary lines re-solved, inner iterations.                              */
 /* lines_out (nullable, n x k x 4): each agent's half-planes (q, d), zero   */
 /* past its neighbour count; pref_out (nullable, n x 2): desired velocity.  */
 /* ------------------------------------------------------------------------ */
@@ -567,12 +569,12 @@ int oracle_step(int n, const float *px, const float *py, const float *vx, const 
             }
             double nvx, nvy;
             const int fail = lp2_mode(L, m, vmax, prx, pry, 0, 0.0, 0.0, prm->eps, &nvx, &nvy,
-                                      &w[3], &w[4]);
+                                      &w[3], &w[4], &w[5]);
             uint8_t st = 0;
             if (fail < m) {
-                lp3(L, m, fail, vmax, prx, pry, prm->eps, &nvx, &nvy, &w[6], &w[7]);
+                lp3(L, m, fail, vmax, prx, pry, prm->eps, &nvx, &nvy, &w[7]);
                 st = 1;
-                w[5] = 1;
+                w[6] = 1;
             }
             ovx[i] = nvx;
             ovy[i] = nvy;

@@ -166,8 +166,9 @@ int orca_build_grid(const orca_agents_in *in, int32_t n, const orca_params *para
     return ORCA_OK;
 }
 
-int orca_step(const orca_agents_in *in, const orca_agents_out *out, int32_t n,
-              const orca_params *params, void *ws, size_t ws_bytes, hipStream_t stream)
+int orca_step_ex(const orca_agents_in *in, const orca_agents_out *out, int32_t n,
+                 const orca_params *params, void *ws, size_t ws_bytes,
+                 const orca_step_events *events, hipStream_t stream)
 {
     Layout L{};
     int rc = prepare(n, params, ws, ws_bytes, L);
@@ -177,9 +178,21 @@ int orca_step(const orca_agents_in *in, const orca_agents_out *out, int32_t n,
     rc = check_out(out);
     if (rc != ORCA_OK) return rc;
     const Work w = bind(L, ws);
+    if (events && events->grid_begin && hipEventRecord(events->grid_begin, stream) != hipSuccess)
+        return ORCA_EHIP;
     if (launch_grid_build(*in, n, *params, L, w, stream) != hipSuccess) return ORCA_EHIP;
+    if (events && events->step_begin && hipEventRecord(events->step_begin, stream) != hipSuccess)
+        return ORCA_EHIP;
     if (launch_step(*in, *out, n, *params, L, w, stream) != hipSuccess) return ORCA_EHIP;
+    if (events && events->step_end && hipEventRecord(events->step_end, stream) != hipSuccess)
+        return ORCA_EHIP;
     return ORCA_OK;
+}
+
+int orca_step(const orca_agents_in *in, const orca_agents_out *out, int32_t n,
+              const orca_params *params, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    return orca_step_ex(in, out, n, params, ws, ws_bytes, nullptr, stream);
 }
 
 const char *orca_status_string(int code)

@@ -123,6 +123,7 @@ __global__ __launch_bounds__(kBlock) void k_grid_setup(const float4 *__restrict_
     g.ny = (int)fy;
     g.m = m;
     g.n_cells = g.nx * g.ny;
+    g.cs_d = cs;
     g.inv_cs = 1.0 / cs;
     g.rn2 = (double)rn * (double)rn;
     g.cell_base = 0;

@@ -22,6 +22,7 @@ struct GridMeta {
     int nx, ny;        // cells per axis
     int m;             // stencil radius in cells: in-range pairs are <= m cells apart
     int n_cells;       // nx * ny
+    double cs_d;       // cs in double (the value inv_cs was derived from)
     double inv_cs;     // 1 / cs, for the FP64 cell coordinates
     double rn2;        // rn * rn in double (exact)
     int cell_base;     // first global cell id of this scene (batched form)

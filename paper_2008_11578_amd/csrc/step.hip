@@ -57,66 +57,212 @@ __device__ __forceinline__ double nb_key(float xi, float yi, float xj, float yj)
     return dx * dx + dy * dy;
 }
 
-// Exact k-nearest selection into a sorted register list of capacity K.
-// Returns the number of entries found (<= K).
+// ---------------------------------------------------------------------------
+// Exact k-nearest selection.
+//
+// Candidates are taken row by row from the cell stencil; each row is clipped
+// to the chord of the neighbour circle at the row's nearest y (FP64, with a
+// margin of 1e-6 cell on every bound, far above the rounding of the cell
+// coordinates), so every agent with key < R_n^2 is visited.
+//
+// Pass 1 counts the in-range candidates of the lane in kBins bins of equal
+// area (bin = floor(key * kBins / R_n^2), monotone in the key); the counts
+// are 8-bit fields of two 64-bit registers.  The first bin b* at which the
+// running count reaches k is the threshold: every candidate of a lower bin is
+// among the k nearest and the rest of the k nearest lie in bin b*.
+// Pass 2 scatters the candidates of bins <= b* into the lane's LDS column in
+// bin order (bucket offsets are 8-bit fields too), and an insertion pass
+// orders each bucket.  Buffer entries are (float(key) bits << 32 | cell-order
+// position): a strict order of the FP32-rounded keys implies the same order
+// of the FP64 keys (rounding is monotone); equal FP32 keys are resolved by
+// recomputing the FP64 keys and then the caller indices.
+// A lane whose counts could overflow (> 255 in range) or whose buckets do
+// not fit the buffer selects by repeated minimum instead (exact, slower).
+// ---------------------------------------------------------------------------
+constexpr int kBins = 16;
+
 template <int K>
-__device__ __forceinline__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
-                                          const float4 *__restrict__ s0, float xi, float yi,
-                                          int self, double (&key)[K], int (&jj)[K],
-                                          int (&pos)[K])
+struct KnnShape {
+    static constexpr int kSlots = K < 8 ? 8 : K;  // 16-byte LDS slots per lane
+    static constexpr int kCap = 2 * kSlots;       // buffer entries per lane
+};
+
+// Entry e of lane `tid` inside a [slot][BLOCK] float4 array viewed as u64.
+template <int BLOCK>
+__device__ __forceinline__ int buf_idx(int e, int tid)
 {
-#pragma unroll
-    for (int q = 0; q < K; ++q) {
-        key[q] = INFINITY;
-        jj[q] = INT_MAX;
-        pos[q] = -1;
-    }
-    const int cx = cell_axis(xi, g.x0, g.inv_cs, g.nx);
-    const int cy = cell_axis(yi, g.y0, g.inv_cs, g.ny);
-    const int ylo = cy - g.m < 0 ? 0 : cy - g.m;
-    const int yhi = cy + g.m > g.ny - 1 ? g.ny - 1 : cy + g.m;
-    const int xlo = cx - g.m < 0 ? 0 : cx - g.m;
-    const int xhi = cx + g.m > g.nx - 1 ? g.nx - 1 : cx + g.m;
-    for (int yy = ylo; yy <= yhi; ++yy) {
-        const int row = g.cell_base + yy * g.nx;
-        const uint32_t a = start[row + xlo];
-        uint32_t b = start[row + xhi + 1];
-        if (b > g.seg_end) b = g.seg_end;  // defensive: stay inside the scene
-        for (uint32_t t = a; t < b; ++t) {
+    return (e >> 1) * (2 * BLOCK) + 2 * tid + (e & 1);
+}
+
+__device__ __forceinline__ uint64_t pack_entry(double key, uint32_t t)
+{
+    return ((uint64_t)__float_as_uint((float)key) << 32) | (uint64_t)t;
+}
+
+// Strict (key, caller index) order of two buffer entries.
+__device__ __forceinline__ bool entry_less(uint64_t ea, uint64_t eb, const float4 *__restrict__ s0,
+                                           float xi, float yi)
+{
+    const uint32_t ha = (uint32_t)(ea >> 32), hb = (uint32_t)(eb >> 32);
+    if (ha != hb) return ha < hb;
+    const float4 ca = s0[(uint32_t)ea];
+    const float4 cb = s0[(uint32_t)eb];
+    const double ka = nb_key(xi, yi, ca.x, ca.y);
+    const double kb = nb_key(xi, yi, cb.x, cb.y);
+    if (ka != kb) return ka < kb;
+    return __float_as_int(ca.z) < __float_as_int(cb.z);
+}
+
+// Grid rows that can hold an agent within R_n of y.
+__device__ __forceinline__ void row_span(const GridMeta &g, double yd, int &ya, int &yb)
+{
+    const double rn = sqrt(g.rn2);
+    const double ua = floor((yd - rn - (double)g.y0) * g.inv_cs - 1e-6);
+    const double ub = floor((yd + rn - (double)g.y0) * g.inv_cs + 1e-6);
+    ya = (int)fmin(fmax(ua, 0.0), (double)(g.ny - 1));
+    yb = (int)fmin(fmax(ub, 0.0), (double)(g.ny - 1));
+}
+
+// Cell-order range of row yy clipped to the chord; false when empty.
+__device__ __forceinline__ bool row_range(const GridMeta &g, const uint32_t *__restrict__ start,
+                                          double xd, double yd, int yy, uint32_t &a, uint32_t &b)
+{
+    const double ylo = (double)g.y0 + (double)yy * g.cs_d;
+    const double dy = fmax(fmax(ylo - yd, yd - (ylo + g.cs_d)) - 1e-6 * g.cs_d, 0.0);
+    const double h2 = g.rn2 - dy * dy;
+    if (!(h2 > 0.0)) return false;
+    const double hw = sqrt(h2);
+    const double ua = floor((xd - hw - (double)g.x0) * g.inv_cs - 1e-6);
+    const double ub = floor((xd + hw - (double)g.x0) * g.inv_cs + 1e-6);
+    const int xa = (int)fmin(fmax(ua, 0.0), (double)(g.nx - 1));
+    const int xb = (int)fmin(fmax(ub, 0.0), (double)(g.nx - 1));
+    const int row = g.cell_base + yy * g.nx;
+    a = start[row + xa];
+    b = start[row + xb + 1];
+    if (b > g.seg_end) b = g.seg_end;  // defensive: stay inside the scene
+    return a < b;
+}
+
+// Selects the (at most K) nearest agents of the lane into entries [0, m) of
+// its LDS buffer, ascending; returns m.
+template <int K, int BLOCK>
+__device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
+                          const float4 *__restrict__ s0, float xi, float yi, int self,
+                          uint64_t *buf, int tid)
+{
+    constexpr int kCap = KnnShape<K>::kCap;
+    const double xd = xi, yd = yi;
+    const double bscale = (double)kBins / g.rn2;
+    int ya, yb;
+    row_span(g, yd, ya, yb);
+
+    // pass 1: per-bin counts
+    uint64_t hlo = 0, hhi = 0;
+    uint32_t total = 0;
+    for (int yy = ya; yy <= yb; ++yy) {
+        uint32_t ra, rb;
+        if (!row_range(g, start, xd, yd, yy, ra, rb)) continue;
+        for (uint32_t t = ra; t < rb; ++t) {
             const float4 c = s0[t];
-            const int j = __float_as_int(c.z);
-            const double kk = nb_key(xi, yi, c.x, c.y);
-            const bool better = kk < key[K - 1] || (kk == key[K - 1] && j < jj[K - 1]);
-            if (kk < g.rn2 && j != self && better) {
-                // insertion from the tail: slot q takes slot q-1 while the
-                // candidate is smaller than it, else the candidate (once)
-                bool lt_q = true;
-#pragma unroll
-                for (int q = K - 1; q > 0; --q) {
-                    const bool lt_p = kk < key[q - 1] || (kk == key[q - 1] && j < jj[q - 1]);
-                    if (lt_p) {
-                        key[q] = key[q - 1];
-                        jj[q] = jj[q - 1];
-                        pos[q] = pos[q - 1];
-                    } else if (lt_q) {
-                        key[q] = kk;
-                        jj[q] = j;
-                        pos[q] = (int)t;
-                    }
-                    lt_q = lt_p;
-                }
-                if (lt_q) {
-                    key[0] = kk;
-                    jj[0] = j;
-                    pos[0] = (int)t;
-                }
+            const double key = nb_key(xi, yi, c.x, c.y);
+            if (key < g.rn2 && __float_as_int(c.z) != self) {
+                const int bin = min((int)(key * bscale), kBins - 1);
+                const uint64_t inc = 1ull << ((bin & 7) * 8);
+                hlo += bin < 8 ? inc : 0ull;
+                hhi += bin < 8 ? 0ull : inc;
+                ++total;
             }
         }
     }
-    int found = 0;
+
+    // threshold bin and bucket offsets
+    uint64_t olo = 0, ohi = 0;
+    uint32_t cum = 0, take = 0;
+    int bstar = kBins - 1;
+    bool found = false;
 #pragma unroll
-    for (int q = 0; q < K; ++q) found += pos[q] >= 0 ? 1 : 0;
-    return found;
+    for (int b = 0; b < kBins; ++b) {
+        const uint32_t cnt = (uint32_t)(((b < 8 ? hlo : hhi) >> ((b & 7) * 8)) & 0xffull);
+        if (b < 8)
+            olo |= (uint64_t)(cum & 0xffu) << (b * 8);
+        else
+            ohi |= (uint64_t)(cum & 0xffu) << ((b - 8) * 8);
+        cum += cnt;
+        if (!found && cum >= (uint32_t)K) {
+            found = true;
+            bstar = b;
+            take = cum;
+        }
+    }
+    if (!found) take = total;
+
+    if (total <= 255u && take <= (uint32_t)kCap) {
+        // pass 2: bucket scatter of bins <= b*
+        for (int yy = ya; yy <= yb; ++yy) {
+            uint32_t ra, rb;
+            if (!row_range(g, start, xd, yd, yy, ra, rb)) continue;
+            for (uint32_t t = ra; t < rb; ++t) {
+                const float4 c = s0[t];
+                const double key = nb_key(xi, yi, c.x, c.y);
+                if (key < g.rn2 && __float_as_int(c.z) != self) {
+                    const int bin = min((int)(key * bscale), kBins - 1);
+                    if (bin <= bstar) {
+                        const int sh = (bin & 7) * 8;
+                        const uint32_t slot = (uint32_t)(((bin < 8 ? olo : ohi) >> sh) & 0xffull);
+                        const uint64_t inc = 1ull << sh;
+                        olo += bin < 8 ? inc : 0ull;
+                        ohi += bin < 8 ? 0ull : inc;
+                        if (slot < (uint32_t)kCap)  // always true: both passes count alike
+                            buf[buf_idx<BLOCK>((int)slot, tid)] = pack_entry(key, t);
+                    }
+                }
+            }
+        }
+        // order inside the buckets (bins are already in order)
+        for (int p = 1; p < (int)take; ++p) {
+            const uint64_t e = buf[buf_idx<BLOCK>(p, tid)];
+            int q = p - 1;
+            while (q >= 0) {
+                const uint64_t f = buf[buf_idx<BLOCK>(q, tid)];
+                if (!entry_less(e, f, s0, xi, yi)) break;
+                buf[buf_idx<BLOCK>(q + 1, tid)] = f;
+                --q;
+            }
+            buf[buf_idx<BLOCK>(q + 1, tid)] = e;
+        }
+        return take < (uint32_t)K ? (int)take : K;
+    }
+
+    // fallback: repeated minimum over all candidates, strictly above the last pick
+    double lk = -1.0;
+    int lj = -1;
+    int m = 0;
+    for (; m < K; ++m) {
+        double bk = INFINITY;
+        int bj = INT_MAX;
+        uint32_t bt = 0;
+        for (int yy = ya; yy <= yb; ++yy) {
+            uint32_t ra, rb;
+            if (!row_range(g, start, xd, yd, yy, ra, rb)) continue;
+            for (uint32_t t = ra; t < rb; ++t) {
+                const float4 c = s0[t];
+                const int j = __float_as_int(c.z);
+                const double key = nb_key(xi, yi, c.x, c.y);
+                const bool above = key > lk || (key == lk && j > lj);
+                const bool below = key < bk || (key == bk && j < bj);
+                if (key < g.rn2 && j != self && above && below) {
+                    bk = key;
+                    bj = j;
+                    bt = t;
+                }
+            }
+        }
+        if (bj == INT_MAX) break;
+        buf[buf_idx<BLOCK>(m, tid)] = pack_entry(bk, bt);
+        lk = bk;
+        lj = bj;
+    }
+    return m;
 }
 
 // ORCA_{A|B} as (q.x, q.y, d.x, d.y); permitted side det(d, v - q) >= 0.
@@ -128,7 +274,9 @@ __device__ __forceinline__ int knn_select(const GridMeta &g, const uint32_t *__r
 //  - overlapping (|P| <= R): the horizon becomes dt and only the disc is used;
 //    w = 0 takes the normal (+1, 0) if A's caller index is the smaller one,
 //    else (-1, 0).
-//  - q = v_A + f u, d = (n.y, -n.x).
+//  - q = v_A + f u, d = (n.y, -n.x).  q is kept as this sum: with f = 0 all
+//    of an agent's lines then pass exactly through v_A, so a feasible set that
+//    has shrunk to that single point stays feasible in FP32.
 __device__ __forceinline__ float4 halfplane(float pax, float pay, float vax, float vay, float ra,
                                             float pbx, float pby, float vbx, float vby, float rb,
                                             float f, float inv_tau, float inv_dt, bool a_first)
@@ -327,7 +475,7 @@ __device__ __forceinline__ void lp3(const float4 *L, int tid, int m, int fail, f
 template <int K, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a)
 {
-    __shared__ float4 lines[K * BLOCK];
+    __shared__ float4 lines[KnnShape<K>::kSlots * BLOCK];
     const int tid = threadIdx.x;
     const int s = blockIdx.x * BLOCK + tid;
     if (s >= a.n) return;
@@ -338,10 +486,12 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a)
     const float xi = me0.x, yi = me0.y, ri = me0.w, vxi = me1.x, vyi = me1.y;
     const int ci = __float_as_int(me1.z) & 1;
 
-    double key[K];
-    int jj[K], pos[K];
-    const int found = knn_select<K>(g, a.start, a.s0, xi, yi, i, key, jj, pos);
+    uint64_t *buf = reinterpret_cast<uint64_t *>(lines);
+    const int found = knn_select<K, BLOCK>(g, a.start, a.s0, xi, yi, i, buf, tid);
     const int m = found < a.k ? found : a.k;
+    uint32_t pos[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) pos[q] = q < m ? (uint32_t)buf[buf_idx<BLOCK>(q, tid)] : 0u;
 
     const float inv_tau = 1.0f / a.tau, inv_dt = 1.0f / a.dt;
     const float fa = ci ? a.f10 : a.f00;  // f[ci][0]
@@ -353,7 +503,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a)
             const float4 b1 = a.s1[pos[q]];
             const float f = (__float_as_int(b1.z) & 1) ? fb : fa;
             lines[q * BLOCK + tid] = halfplane(xi, yi, vxi, vyi, ri, b0.x, b0.y, b1.x, b1.y, b0.w,
-                                               f, inv_tau, inv_dt, i < jj[q]);
+                                               f, inv_tau, inv_dt, i < __float_as_int(b0.z));
         }
     }
 
@@ -382,22 +532,24 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a)
     if (a.out.status) a.out.status[i] = st;
 }
 
-template <int K>
-__global__ __launch_bounds__(256) void k_knn_export(StepArgs a)
+template <int K, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_knn_export(StepArgs a)
 {
-    const int s = blockIdx.x * 256 + threadIdx.x;
+    __shared__ float4 lds[KnnShape<K>::kSlots * BLOCK];
+    const int tid = threadIdx.x;
+    const int s = blockIdx.x * BLOCK + tid;
     if (s >= a.n) return;
     const GridMeta g = *a.meta;
     const float4 me0 = a.s0[s];
     const int i = __float_as_int(me0.z);
-    double key[K];
-    int jj[K], pos[K];
-    const int found = knn_select<K>(g, a.start, a.s0, me0.x, me0.y, i, key, jj, pos);
+    uint64_t *buf = reinterpret_cast<uint64_t *>(lds);
+    const int found = knn_select<K, BLOCK>(g, a.start, a.s0, me0.x, me0.y, i, buf, tid);
     const int m = found < a.k ? found : a.k;
-    int32_t *row = a.nbr ? a.nbr + (int64_t)i * a.k : nullptr;
-#pragma unroll
-    for (int q = 0; q < K; ++q)
-        if (row && q < a.k) row[q] = q < m ? jj[q] : -1;
+    if (a.nbr) {
+        int32_t *row = a.nbr + (int64_t)i * a.k;
+        for (int q = 0; q < a.k; ++q)
+            row[q] = q < m ? __float_as_int(a.s0[(uint32_t)buf[buf_idx<BLOCK>(q, tid)]].z) : -1;
+    }
     if (a.cnt) a.cnt[i] = m;
 }
 
@@ -439,8 +591,8 @@ void launch_step_k(const StepArgs &a, hipStream_t stream)
 template <int K>
 void launch_knn_k(const StepArgs &a, hipStream_t stream)
 {
-    const int nb = (a.n + 255) / 256;
-    hipLaunchKernelGGL((k_knn_export<K>), dim3(nb), dim3(256), 0, stream, a);
+    const int nb = (a.n + kStepBlock - 1) / kStepBlock;
+    hipLaunchKernelGGL((k_knn_export<K, kStepBlock>), dim3(nb), dim3(kStepBlock), 0, stream, a);
 }
 
 }  // namespace

@@ -45,6 +45,11 @@ class AgentsOut(ctypes.Structure):
     _fields_ = [(k, ctypes.c_void_p) for k in ("px", "py", "vx", "vy", "status")]
 
 
+class StepEvents(ctypes.Structure):
+    _fields_ = [("grid_begin", ctypes.c_void_p), ("step_begin", ctypes.c_void_p),
+                ("step_end", ctypes.c_void_p)]
+
+
 _lib = None
 
 
@@ -68,6 +73,10 @@ def lib() -> ctypes.CDLL:
         L.orca_step.restype = ctypes.c_int
         L.orca_step.argtypes = [ctypes.POINTER(AgentsIn), ctypes.POINTER(AgentsOut), i32,
                                 ctypes.POINTER(OrcaParams), vp, sz, vp]
+        L.orca_step_ex.restype = ctypes.c_int
+        L.orca_step_ex.argtypes = [ctypes.POINTER(AgentsIn), ctypes.POINTER(AgentsOut), i32,
+                                   ctypes.POINTER(OrcaParams), vp, sz,
+                                   ctypes.POINTER(StepEvents), vp]
         L.orca_status_string.restype = ctypes.c_char_p
         L.orca_status_string.argtypes = [ctypes.c_int]
         L.orca_version.restype = ctypes.c_char_p
@@ -194,9 +203,11 @@ def build_grid(state: State, params, ws: Workspace, want_neighbors: bool = True,
 
 
 def step(state: State, params, ws: Workspace, out: Optional[State] = None,
-         status: Optional[torch.Tensor] = None, stream=None) -> State:
+         status: Optional[torch.Tensor] = None, stream=None, events=None) -> State:
     """One ORCA step.  ``out`` (default: a copy of ``state``) receives the new
-    positions and velocities; it may be ``state`` itself (in-place step)."""
+    positions and velocities; it may be ``state`` itself (in-place step).
+    ``events``: optional (grid_begin, step_begin, step_end) raw hipEvent_t
+    handles recorded around the phases (timing only)."""
     p = make_params(params)
     n = state.n
     if out is None:
@@ -207,8 +218,13 @@ def step(state: State, params, ws: Workspace, out: Optional[State] = None,
         _check(getattr(out, k), "out." + k, torch.float32, n)
     ain = state.agents_in()
     aout = AgentsOut(_ptr(out.px), _ptr(out.py), _ptr(out.vx), _ptr(out.vy), _ptr(status))
-    rc = lib().orca_step(ctypes.byref(ain), ctypes.byref(aout), n, ctypes.byref(p), ws.ptr(),
-                         ws.nbytes, _stream_handle(stream))
+    if events is None:
+        rc = lib().orca_step(ctypes.byref(ain), ctypes.byref(aout), n, ctypes.byref(p),
+                             ws.ptr(), ws.nbytes, _stream_handle(stream))
+    else:
+        ev = StepEvents(*events)
+        rc = lib().orca_step_ex(ctypes.byref(ain), ctypes.byref(aout), n, ctypes.byref(p),
+                                ws.ptr(), ws.nbytes, ctypes.byref(ev), _stream_handle(stream))
     if rc != ORCA_OK:
         raise OrcaError("orca_step", rc)
     return out
