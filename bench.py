@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import ctypes
+import dataclasses
 import hashlib
 import json
 import os
@@ -140,10 +141,16 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--cpu-steps", type=int, default=6,
+    ap.add_argument("--cpu-steps", type=int, default=40,
                     help="oracle steps in the CPU-baseline sample (0 disables it)")
     ap.add_argument("--side", type=int, default=1024,
                     help="lattice side of the crossing workload (1024 -> 1,048,576 agents)")
+    ap.add_argument("--cell-size", type=float, default=1.5,
+                    help="grid cell size in m (1.5 = R_n/2, the fastest measured for this "
+                         "workload; 0 = library default R_n)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (5 times) and exit: the "
+                         "reference kernel for scaling HBM counters")
     args = ap.parse_args(argv)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -161,9 +168,17 @@ def main(argv=None):
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
     torch.cuda.set_device(0)
+    if args.calibrate_copy > 0:
+        a = torch.empty(args.calibrate_copy << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] copied {args.calibrate_copy} MiB 5 times")
+        return 0
     sc = scenarios.c3_crossing(side_count=args.side)
     n = sc.n
-    params = sc.params
+    params = dataclasses.replace(sc.params, cell_size=args.cell_size)
     log(f"[bench] workload {sc.name}: n={n}, k={params.max_neighbors}, R_n={params.neighbor_dist}")
     state = orca.State.from_arrays(sc)
     nxt = state.clone()
@@ -237,6 +252,7 @@ def main(argv=None):
         "config": {"workload": f"dense four-way crossing, {n} pedestrians, 700 m square, "
                                f"R_n 3 m, k 20, dt 0.1 s, tau 2 s",
                    "agents": n, "max_neighbors": params.max_neighbors,
+                   "cell_size": params.cell_size,
                    "grid_ms": g_ms, "step_kernel_ms": k_ms, "lp3_share_end": lp3_share},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -47,6 +47,18 @@ __device__ __forceinline__ int cell_axis(float v, float v0, double inv_cs, int n
     return (int)c;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Remapping dispatch index b to a logical tile so that every XCD works
+// on one contiguous range of tiles keeps neighbouring agents (which read each
+// other's state) inside one L2.  Bijective on [0, nb).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile(int b, int nb)
+{
+    const int q = nb / kXcds, r = nb % kXcds;
+    const int x = b % kXcds;
+    return x * q + (x < r ? x : r) + b / kXcds;
+}
+
 Layout make_layout(int64_t n, int64_t n_scenes, int64_t max_cells);
 
 inline int64_t default_max_cells(int64_t n) { return n * 2 > 4096 ? n * 2 : 4096; }

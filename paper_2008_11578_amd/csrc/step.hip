@@ -113,6 +113,23 @@ __device__ __forceinline__ bool entry_less(uint64_t ea, uint64_t eb, const float
     return __float_as_int(ca.z) < __float_as_int(cb.z);
 }
 
+// Visits the cell-order candidates [ra, rb) in order, keeping four
+// independent loads in flight per lane.
+template <class F>
+__device__ __forceinline__ void scan_range(const float4 *__restrict__ s0, uint32_t ra, uint32_t rb,
+                                           F &&visit)
+{
+    uint32_t t = ra;
+    for (; t + 4 <= rb; t += 4) {
+        const float4 c0 = s0[t], c1 = s0[t + 1], c2 = s0[t + 2], c3 = s0[t + 3];
+        visit(c0, t);
+        visit(c1, t + 1);
+        visit(c2, t + 2);
+        visit(c3, t + 3);
+    }
+    for (; t < rb; ++t) visit(s0[t], t);
+}
+
 // Grid rows that can hold an agent within R_n of y.
 __device__ __forceinline__ void row_span(const GridMeta &g, double yd, int &ya, int &yb)
 {
@@ -162,8 +179,7 @@ __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
     for (int yy = ya; yy <= yb; ++yy) {
         uint32_t ra, rb;
         if (!row_range(g, start, xd, yd, yy, ra, rb)) continue;
-        for (uint32_t t = ra; t < rb; ++t) {
-            const float4 c = s0[t];
+        scan_range(s0, ra, rb, [&](const float4 &c, uint32_t) {
             const double key = nb_key(xi, yi, c.x, c.y);
             if (key < g.rn2 && __float_as_int(c.z) != self) {
                 const int bin = min((int)(key * bscale), kBins - 1);
@@ -172,7 +188,7 @@ __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
                 hhi += bin < 8 ? 0ull : inc;
                 ++total;
             }
-        }
+        });
     }
 
     // threshold bin and bucket offsets
@@ -201,8 +217,7 @@ __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
         for (int yy = ya; yy <= yb; ++yy) {
             uint32_t ra, rb;
             if (!row_range(g, start, xd, yd, yy, ra, rb)) continue;
-            for (uint32_t t = ra; t < rb; ++t) {
-                const float4 c = s0[t];
+            scan_range(s0, ra, rb, [&](const float4 &c, uint32_t t) {
                 const double key = nb_key(xi, yi, c.x, c.y);
                 if (key < g.rn2 && __float_as_int(c.z) != self) {
                     const int bin = min((int)(key * bscale), kBins - 1);
@@ -216,7 +231,7 @@ __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
                             buf[buf_idx<BLOCK>((int)slot, tid)] = pack_entry(key, t);
                     }
                 }
-            }
+            });
         }
         // order inside the buckets (bins are already in order)
         for (int p = 1; p < (int)take; ++p) {
@@ -477,7 +492,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a)
 {
     __shared__ float4 lines[KnnShape<K>::kSlots * BLOCK];
     const int tid = threadIdx.x;
-    const int s = blockIdx.x * BLOCK + tid;
+    const int s = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + tid;
     if (s >= a.n) return;
     const GridMeta g = *a.meta;
     const float4 me0 = a.s0[s];
@@ -537,7 +552,7 @@ __global__ __launch_bounds__(BLOCK) void k_knn_export(StepArgs a)
 {
     __shared__ float4 lds[KnnShape<K>::kSlots * BLOCK];
     const int tid = threadIdx.x;
-    const int s = blockIdx.x * BLOCK + tid;
+    const int s = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + tid;
     if (s >= a.n) return;
     const GridMeta g = *a.meta;
     const float4 me0 = a.s0[s];
