@@ -55,7 +55,7 @@ def log(*a):
 
 def source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("step.hip", "orca_internal.h"):
+    for f in ("step.hip", "orca_device.h", "orca_internal.h"):
         with open(os.path.join(ROOT, "paper_2008_11578_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -136,6 +136,86 @@ def cpu_baseline(state_start, state_end, params, n, steps):
     return rate, elapsed, threads, w_start, o_end["work"]
 
 
+def capture_loop(step_fn, a, b, steps):
+    """Records `steps` ping-pong steps a->b->a... into one HIP graph; returns
+    (graph, final state)."""
+    import torch
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(graph, stream=stream):
+            x, y = a, b
+            for _ in range(steps):
+                step_fn(x, y)
+                x, y = y, x
+    torch.cuda.synchronize()
+    return graph, x
+
+
+def bench_batched(steps: int):
+    """512 uneven scenes (about 5.6M agents) per step: the autotuned batched
+    step captured as a `steps`-step graph, against 512 sequential single-scene
+    steps captured as a graph."""
+    import torch
+    from paper_2008_11578_amd import autotune, orca, scenarios
+    sc = scenarios.c4_batched()
+    S = len(sc.scene_params)
+    n = sc.n
+    st = orca.State.from_arrays(sc)
+    nxt = st.clone()
+    ws = orca.Workspace(n, n_scenes=S)
+    tuned = autotune.tune_batched(st, sc.scene_off, sc.scene_params, ws, reps=3, use_cache=False)
+    batch = orca.Batch(sc.scene_off, tuned["params"], mode=tuned["mode"])
+    graph, _ = capture_loop(lambda x, y: orca.step_batched(x, batch, ws, out=y), st, nxt, steps)
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    graph.replay()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    assert int(batch.error.item()) == 0
+    # per-scene baseline: one orca_step per scene, sequentially, in a graph
+    parts = []
+    for s in range(S):
+        a, z = int(sc.scene_off[s]), int(sc.scene_off[s + 1])
+        parts.append((orca.State(**{k: getattr(st, k)[a:z] for k in orca.STATE_FIELDS}),
+                      orca.State(**{k: getattr(nxt, k)[a:z] for k in orca.STATE_FIELDS}),
+                      orca.Workspace(z - a), tuned["params"][s]))
+
+    def per_scene(x_is_st):
+        for xs, ys, wss, p in parts:
+            if x_is_st:
+                orca.step(xs, p, wss, out=ys)
+            else:
+                orca.step(ys, p, wss, out=xs)
+
+    per_scene(True)
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    g2 = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(g2, stream=stream):
+            per_scene(True)
+            per_scene(False)
+    torch.cuda.synchronize()
+    g2.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g2.replay()
+    torch.cuda.synchronize()
+    ms_ps = (time.perf_counter() - t0) * 1e3 / 2
+    log(f"[bench] batched {S} scenes, {n} agents: {ms:.3f} ms/step (graph of {steps}), "
+        f"per-scene {ms_ps:.3f} ms/step, tuned factor {tuned['factor']:.3f} mode {tuned['mode']}")
+    return {"metric": "scene-steps/s (512 uneven scenes, one batched step per graph node set)",
+            "scenes": S, "agents": n, "ms_per_step": ms,
+            "scene_steps_per_s": S / (ms * 1e-3), "agent_steps_per_s": n / (ms * 1e-3),
+            "per_scene_ms_per_step": ms_ps, "speedup_vs_per_scene": ms_ps / ms,
+            "graph_steps": steps, "tuned": {"cell_factor": tuned["factor"],
+                                             "mode": tuned["mode"]}}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +228,8 @@ def main(argv=None):
     ap.add_argument("--cell-size", type=float, default=1.5,
                     help="grid cell size in m (1.5 = R_n/2, the fastest measured for this "
                          "workload; 0 = library default R_n)")
+    ap.add_argument("--batched-steps", type=int, default=100,
+                    help="graph-captured steps of the 512-scene batched form (0 skips it)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) and exit: the "
                          "reference kernel for scaling HBM counters")
@@ -236,6 +318,8 @@ def main(argv=None):
                 "hbm_algorithmic_GBs": STEP_BYTES_PER_AGENT * n / (k_ms * 1e-3) / 1e9,
                 "hbm_peak_GBs": HBM_PEAK_GBS, "source_hash": kh}
 
+    batched = bench_batched(args.batched_steps) if args.batched_steps > 0 else None
+
     out = {
         "metric": "agent-steps/sec at 1M agents (ORCA+LP)",
         "value": value,
@@ -256,6 +340,7 @@ def main(argv=None):
                    "grid_ms": g_ms, "step_kernel_ms": k_ms, "lp3_share_end": lp3_share},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -89,9 +89,11 @@ typedef struct {
 
 /* Bytes of workspace needed for n agents (plain step / grid), or for a
  * batch whose total agent count is n and scene count n_scenes (batched step;
- * pass n_scenes = 0 for the plain step).  max_cells bounds the grid cells
- * (0 selects a default of max(2n, 4096)); when a scene's bounding box would
- * need more cells the library enlarges the cell size on the device. */
+ * pass n_scenes = 0 for the plain step).  For the plain step max_cells bounds
+ * the grid cells (0 selects a default of max(2n, 4096)); a batch always gets
+ * 2 cells per agent plus 64 per scene (max_cells ignored).  When a scene's
+ * bounding box would need more cells the library enlarges the cell size on
+ * the device. */
 size_t orca_workspace_bytes(int32_t n, int32_t n_scenes, int32_t max_cells);
 
 /* Zero-fills a workspace on `stream` (a fill kernel, no memset node). */
@@ -126,6 +128,32 @@ typedef struct {
 int orca_step_ex(const orca_agents_in *in, const orca_agents_out *out, int32_t n,
                  const orca_params *params, void *ws, size_t ws_bytes,
                  const orca_step_events *events, hipStream_t stream);
+
+/* Description of a batch of independent scenes for orca_step_batched.
+ * Scene s owns the agents [scene_off[s], scene_off[s+1]) of the agent arrays
+ * and uses params[s]; agents of different scenes never interact.  This
+ * batched form is not part of the paper (which simulates one scene); it runs
+ * every scene of a step in one set of launches. */
+typedef struct {
+    const int32_t *scene_off;     /* DEVICE, n_scenes + 1 entries, ascending,
+                                     scene_off[0] = 0, scene_off[n_scenes] = n */
+    int32_t n_scenes;             /* >= 1 */
+    const orca_params *params;    /* DEVICE, n_scenes entries (cell_size 0 = R_n) */
+    int32_t max_neighbors;        /* HOST: largest max_neighbors over the scenes,
+                                     1..ORCA_K_MAX (selects the compiled kernel) */
+    int32_t mode;                 /* 0: persistent kernel with per-XCD tile queues
+                                     (default); 1: one workgroup per tile */
+    int32_t *error_flag;          /* DEVICE, nullable: set to 1 (never cleared) when
+                                     an offset or a scene's parameters are invalid;
+                                     the kernels clamp every index regardless */
+} orca_batch;
+
+/* One ORCA step of every scene of a batch.  n is the total agent count; the
+ * workspace must hold orca_workspace_bytes(n, batch->n_scenes, 0) bytes.
+ * Each scene's result equals orca_step on that scene alone (same neighbour
+ * lists and velocities, bit for bit). */
+int orca_step_batched(const orca_agents_in *in, const orca_agents_out *out, int32_t n,
+                      const orca_batch *batch, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Human-readable text for a status code (static storage). */
 const char *orca_status_string(int code);

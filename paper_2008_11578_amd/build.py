@@ -12,8 +12,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liborca.so")
-SOURCES = ["grid.hip", "step.hip", "capi.hip"]
-HEADERS = ["orca_internal.h", os.path.join("..", "..", "include", "orca.h")]
+SOURCES = ["grid.hip", "step.hip", "batch.hip", "capi.hip"]
+HEADERS = ["orca_internal.h", "orca_device.h", os.path.join("..", "..", "include", "orca.h")]
 ARCH = os.environ.get("ORCA_OFFLOAD_ARCH", "gfx950")
 
 

@@ -1,0 +1,267 @@
+// Batched ORCA step: many independent scenes of uneven sizes advanced by one
+// set of launches per step (batched form; not in the paper, which simulates
+// one scene).
+//
+// Scene s owns caller indices [off[s], off[s+1]) and the cells
+// [2 off[s] + 64 s, 2 off[s+1] + 64 (s+1)) of one global cell space, so a
+// single histogram, scan and scatter order every scene at once and each scene
+// stays contiguous in cell order (its agents fill exactly the positions
+// [off[s], off[s+1])).  Agents of different scenes never share a cell and so
+// never see each other.
+//
+// The step kernel is persistent: a grid sized to the device's occupancy
+// whose wavefronts pop 64-agent tiles from eight queues, one per XCD (each
+// over a contiguous range of tiles, so neighbouring agents stay in one L2),
+// and steal from the other queues once their own is drained.  Every queue is
+// a monotone counter, so every wavefront exits.
+#include "orca_device.h"
+
+namespace orca {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kStepBlock = 128;
+constexpr int kTile = 64;
+
+// Scene of caller index i: the largest s with off[s] <= i (off ascending).
+__device__ __forceinline__ int scene_of(const int32_t *__restrict__ off, int S, int i)
+{
+    int lo = 0, hi = S - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int clamp_off(int v, int n) { return v < 0 ? 0 : (v > n ? n : v); }
+
+// (1) one block per scene: bounding box of its agents.  All blocks also clear
+// the histogram and block 0 the tile queues; scene offsets and parameters
+// are checked and any violation is flagged (the kernels stay in bounds
+// regardless: offsets are clamped to [0, n]).
+__global__ __launch_bounds__(kBlock) void k_batch_bbox(const float *__restrict__ px,
+                                                       const float *__restrict__ py, int n,
+                                                       const int32_t *__restrict__ off, int S,
+                                                       const orca_params *__restrict__ prm,
+                                                       float4 *__restrict__ partial,
+                                                       uint32_t *__restrict__ count, int count_len,
+                                                       uint32_t *__restrict__ queue,
+                                                       int32_t *__restrict__ error_flag)
+{
+    const int s = blockIdx.x;
+    const int a = clamp_off(off[s], n), b = clamp_off(off[s + 1], n);
+    float4 bb = make_float4(INFINITY, INFINITY, -INFINITY, -INFINITY);
+    for (int i = a + threadIdx.x; i < b; i += kBlock) {
+        const float x = px[i], y = py[i];
+        bb.x = fminf(bb.x, x);
+        bb.y = fminf(bb.y, y);
+        bb.z = fmaxf(bb.z, x);
+        bb.w = fmaxf(bb.w, y);
+    }
+    const int stride = gridDim.x * kBlock;
+    for (int c = blockIdx.x * kBlock + threadIdx.x; c < count_len; c += stride) count[c] = 0u;
+    if (s == 0 && threadIdx.x < kXcds) queue[threadIdx.x] = 0u;
+    bb = block_bbox<kBlock>(bb);
+    if (threadIdx.x == 0) {
+        partial[s] = bb;
+        if (error_flag) {
+            const orca_params p = prm[s];
+            bool bad = off[s] > off[s + 1] || off[s] < 0 || off[s + 1] > n;
+            if (s == 0) bad = bad || off[0] != 0;
+            if (s == S - 1) bad = bad || off[S] != n;
+            bad = bad || !(p.dt > 0.0f) || !(p.time_horizon > 0.0f) ||
+                  !(p.neighbor_dist > 0.0f) || !(p.cell_size >= 0.0f) ||
+                  p.max_neighbors < 1 || p.max_neighbors > ORCA_K_MAX ||
+                  (p.pref_is_goal != 0 && p.pref_is_goal != 1);
+            if (bad) atomicOr(error_flag, 1);
+        }
+    }
+}
+
+// (2) one thread per scene: grid geometry within the scene's cell budget.
+// meta[S] describes the whole cell space for the scan.
+__global__ __launch_bounds__(kBlock) void k_batch_setup(const float4 *__restrict__ partial,
+                                                        const int32_t *__restrict__ off, int S,
+                                                        int n, const orca_params *__restrict__ prm,
+                                                        GridMeta *__restrict__ meta)
+{
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    if (s == 0) {
+        GridMeta g{};
+        g.n_cells = (int)batched_cells(n, S);
+        g.n = n;
+        g.seg_end = (uint32_t)n;
+        meta[S] = g;
+    }
+    if (s >= S) return;
+    const int a = clamp_off(off[s], n);
+    const int b = max(clamp_off(off[s + 1], n), a);
+    const int budget = 2 * (b - a) + 64;
+    GridMeta g;
+    grid_geometry(partial[s], prm[s].neighbor_dist, prm[s].cell_size, budget, g);
+    // a budget is 2 cells per agent plus 64; the cell ranges of consecutive
+    // scenes tile the global cell space when offsets are valid and stay
+    // inside it otherwise
+    g.cell_base = 2 * a + 64 * s;
+    g.agent_base = a;
+    g.n = b - a;
+    g.seg_end = (uint32_t)b;
+    meta[s] = g;
+}
+
+// (3) scene, cell and rank inside the cell.
+__global__ __launch_bounds__(kBlock) void k_batch_count(const float *__restrict__ px,
+                                                        const float *__restrict__ py, int n,
+                                                        const int32_t *__restrict__ off, int S,
+                                                        const GridMeta *__restrict__ meta,
+                                                        uint32_t *__restrict__ cell,
+                                                        uint32_t *__restrict__ rank,
+                                                        uint32_t *__restrict__ count)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const GridMeta g = meta[scene_of(off, S, i)];
+    const int cx = cell_axis(px[i], g.x0, g.inv_cs, g.nx);
+    const int cy = cell_axis(py[i], g.y0, g.inv_cs, g.ny);
+    const uint32_t c = (uint32_t)(g.cell_base + cx + g.nx * cy);
+    cell[i] = c;
+    rank[i] = atomicAdd(&count[c], 1u);
+}
+
+struct BatchArgs {
+    orca_agents_in in;
+    orca_agents_out out;
+    const GridMeta *meta;
+    const orca_params *prm;
+    const int32_t *off;
+    int S;
+    int n;
+    const uint32_t *start;
+    const float4 *s0;
+    const float4 *s1;
+    uint32_t *queue;
+};
+
+template <int K, int BLOCK>
+__device__ __forceinline__ void batch_agent(const BatchArgs &a, int s, float4 *lines, int tid)
+{
+    const int sc = scene_of(a.off, a.S, s);
+    const GridMeta g = a.meta[sc];
+    const dev::SceneP p = dev::scene_params(a.prm[sc]);
+    dev::step_agent<K, BLOCK>(s, g, p, a.in, a.out, a.start, a.s0, a.s1, lines, tid);
+}
+
+// Persistent step: wavefronts pop 64-agent tiles, first from their XCD's
+// queue (a contiguous eighth of the tiles), then from the others.
+template <int K, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_step_batched(BatchArgs a)
+{
+    __shared__ float4 lines[dev::KnnShape<K>::kSlots * BLOCK];
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int n_tiles = (a.n + kTile - 1) / kTile;
+    const int xcd = blockIdx.x % kXcds;
+    for (int v = 0; v < kXcds; ++v) {
+        const int x = (xcd + v) % kXcds;
+        const int lo = (int)(((int64_t)n_tiles * x) / kXcds);
+        const int hi = (int)(((int64_t)n_tiles * (x + 1)) / kXcds);
+        for (;;) {
+            int t = 0;
+            if (lane == 0) t = (int)atomicAdd(&a.queue[x], 1u);
+            t = __shfl(t, 0, kWave);
+            if (t >= hi - lo) break;
+            const int s = (lo + t) * kTile + lane;
+            if (s < a.n) batch_agent<K, BLOCK>(a, s, lines, tid);
+        }
+    }
+}
+
+// Flat form of the same step: one tile per workgroup wave, XCD-aware order.
+template <int K, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_step_batched_flat(BatchArgs a)
+{
+    __shared__ float4 lines[dev::KnnShape<K>::kSlots * BLOCK];
+    const int tid = threadIdx.x;
+    const int s = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + tid;
+    if (s < a.n) batch_agent<K, BLOCK>(a, s, lines, tid);
+}
+
+// Workgroups of k_step_batched that fit the device at once (cached per
+// instantiation; multiple of the XCD count).
+template <int K, int BLOCK>
+int persistent_grid()
+{
+    static int cached = 0;
+    if (cached) return cached;
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_batched<K, BLOCK>, BLOCK, 0) !=
+        hipSuccess)
+        return 0;
+    int g = cus * (per_cu > 0 ? per_cu : 1);
+    g = (g + kXcds - 1) / kXcds * kXcds;
+    cached = g;
+    return g;
+}
+
+template <int K>
+hipError_t launch_step_batched_k(const BatchArgs &a, int mode, hipStream_t stream)
+{
+    if (mode == 1) {
+        const int nb = (a.n + kStepBlock - 1) / kStepBlock;
+        hipLaunchKernelGGL((k_step_batched_flat<K, kStepBlock>), dim3(nb), dim3(kStepBlock), 0,
+                           stream, a);
+        return hipGetLastError();
+    }
+    const int g = persistent_grid<K, kStepBlock>();
+    if (g <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_step_batched<K, kStepBlock>), dim3(g), dim3(kStepBlock), 0, stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_batched(const orca_agents_in &in, const orca_agents_out &out, int n,
+                          const int32_t *scene_off, int n_scenes, const orca_params *params,
+                          int k_max, const Layout &L, const Work &w, int32_t *error_flag,
+                          int mode, hipStream_t stream)
+{
+    const int S = n_scenes;
+    const int nb = (n + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_batch_bbox, dim3(S), dim3(kBlock), 0, stream, in.px, in.py, n, scene_off,
+                       S, params, w.partial, w.count, (int)L.max_cells, w.queue, error_flag);
+    hipLaunchKernelGGL(k_batch_setup, dim3((S + kBlock - 1) / kBlock), dim3(kBlock), 0, stream,
+                       w.partial, scene_off, S, n, params, w.meta);
+    hipLaunchKernelGGL(k_batch_count, dim3(nb), dim3(kBlock), 0, stream, in.px, in.py, n,
+                       scene_off, S, w.meta, w.cell, w.rank, w.count);
+    hipError_t e = launch_scan_scatter(in, n, L, w, w.meta + S, stream);
+    if (e != hipSuccess) return e;
+    BatchArgs a;
+    a.in = in;
+    a.out = out;
+    a.meta = w.meta;
+    a.prm = params;
+    a.off = scene_off;
+    a.S = S;
+    a.n = n;
+    a.start = w.start;
+    a.s0 = w.s0;
+    a.s1 = w.s1;
+    a.queue = w.queue;
+    if (k_max <= 4) return launch_step_batched_k<4>(a, mode, stream);
+    if (k_max <= 8) return launch_step_batched_k<8>(a, mode, stream);
+    if (k_max <= 10) return launch_step_batched_k<10>(a, mode, stream);
+    if (k_max <= 12) return launch_step_batched_k<12>(a, mode, stream);
+    if (k_max <= 16) return launch_step_batched_k<16>(a, mode, stream);
+    if (k_max <= 20) return launch_step_batched_k<20>(a, mode, stream);
+    if (k_max <= 24) return launch_step_batched_k<24>(a, mode, stream);
+    return launch_step_batched_k<32>(a, mode, stream);
+}
+
+}  // namespace orca

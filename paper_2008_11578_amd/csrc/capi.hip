@@ -14,7 +14,10 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 Layout make_layout(int64_t n, int64_t n_scenes, int64_t max_cells)
 {
     Layout L{};
-    if (max_cells <= 0) max_cells = default_max_cells(n);
+    if (n_scenes > 0)
+        max_cells = batched_cells(n, n_scenes);
+    else if (max_cells <= 0)
+        max_cells = default_max_cells(n);
     const int64_t S = n_scenes > 0 ? n_scenes : 1;
     L.n = n;
     L.n_scenes = S;
@@ -22,9 +25,11 @@ Layout make_layout(int64_t n, int64_t n_scenes, int64_t max_cells)
     L.n_tiles = (max_cells + 1 + kScanTile - 1) / kScanTile;
     size_t o = 0;
     L.meta = o;
-    o = align_up(o + sizeof(GridMeta) * (size_t)S);
+    o = align_up(o + sizeof(GridMeta) * (size_t)(S + 1));
     L.partial = o;
-    o = align_up(o + sizeof(float4) * (size_t)kBboxBlocks * (size_t)S);
+    o = align_up(o + sizeof(float4) * (size_t)(S > kBboxBlocks ? S : kBboxBlocks));
+    L.queue = o;
+    o = align_up(o + sizeof(uint32_t) * kXcds);
     L.cell = o;
     o = align_up(o + sizeof(uint32_t) * (size_t)n);
     L.rank = o;
@@ -49,6 +54,7 @@ Work bind(const Layout &L, void *ws)
     Work w;
     w.meta = (GridMeta *)(b + L.meta);
     w.partial = (float4 *)(b + L.partial);
+    w.queue = (uint32_t *)(b + L.queue);
     w.cell = (uint32_t *)(b + L.cell);
     w.rank = (uint32_t *)(b + L.rank);
     w.count = (uint32_t *)(b + L.count);
@@ -193,6 +199,30 @@ int orca_step(const orca_agents_in *in, const orca_agents_out *out, int32_t n,
               const orca_params *params, void *ws, size_t ws_bytes, hipStream_t stream)
 {
     return orca_step_ex(in, out, n, params, ws, ws_bytes, nullptr, stream);
+}
+
+int orca_step_batched(const orca_agents_in *in, const orca_agents_out *out, int32_t n,
+                      const orca_batch *batch, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (n < 0 || !batch) return ORCA_EINVAL;
+    if (batch->n_scenes < 1 || !batch->scene_off || !batch->params) return ORCA_EINVAL;
+    if (batch->max_neighbors < 1 || batch->max_neighbors > ORCA_K_MAX) return ORCA_ERANGE;
+    if (batch->mode != 0 && batch->mode != 1) return ORCA_EINVAL;
+    if (n == 0) return ORCA_OK;
+    int rc = check_in(in);
+    if (rc != ORCA_OK) return rc;
+    rc = check_out(out);
+    if (rc != ORCA_OK) return rc;
+    if (!ws) return ORCA_EINVAL;
+    if (batched_cells(n, batch->n_scenes) > kMaxCellsCap) return ORCA_EINVAL;
+    const Layout L = make_layout(n, batch->n_scenes, 0);
+    if (L.total > ws_bytes) return ORCA_EWORKSPACE;
+    const Work w = bind(L, ws);
+    if (launch_batched(*in, *out, n, batch->scene_off, batch->n_scenes, batch->params,
+                       batch->max_neighbors, L, w, batch->error_flag, batch->mode,
+                       stream) != hipSuccess)
+        return ORCA_EHIP;
+    return ORCA_OK;
 }
 
 const char *orca_status_string(int code)

@@ -13,42 +13,6 @@ namespace {
 
 constexpr int kBlock = 256;
 
-__device__ __forceinline__ float wave_min(float v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, kWave));
-    return v;
-}
-
-__device__ __forceinline__ float wave_max(float v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
-    return v;
-}
-
-// Block-wide (min x, min y, max x, max y).  Result valid in thread 0.
-__device__ float4 block_bbox(float4 b)
-{
-    __shared__ float4 red[kBlock / kWave];
-    b.x = wave_min(b.x);
-    b.y = wave_min(b.y);
-    b.z = wave_max(b.z);
-    b.w = wave_max(b.w);
-    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-    if (lane == 0) red[wid] = b;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int k = 1; k < kBlock / kWave; ++k) {
-            b.x = fminf(b.x, red[k].x);
-            b.y = fminf(b.y, red[k].y);
-            b.z = fmaxf(b.z, red[k].z);
-            b.w = fmaxf(b.w, red[k].w);
-        }
-    }
-    return b;
-}
-
 // (1) partial bounding boxes; also clears the cell histogram for (3).
 __global__ __launch_bounds__(kBlock) void k_bbox_partial(const float *__restrict__ px,
                                                          const float *__restrict__ py, int n,
@@ -66,15 +30,11 @@ __global__ __launch_bounds__(kBlock) void k_bbox_partial(const float *__restrict
         b.w = fmaxf(b.w, y);
     }
     for (int c = blockIdx.x * kBlock + threadIdx.x; c < count_len; c += stride) count[c] = 0u;
-    b = block_bbox(b);
+    b = block_bbox<kBlock>(b);
     if (threadIdx.x == 0) partial[blockIdx.x] = b;
 }
 
-// (2) one block: final bounding box and grid geometry.
-//   m  = stencil radius in cells, ceil(R_n / requested cell size)
-//   cs = max(requested, R_n / m) * (1 + 1e-5), so that m * cs > R_n with a
-//        margin far above the rounding of the FP64 cell coordinates
-//   the cell size grows (and m is re-derived) until nx * ny <= max_cells.
+// (2) one block: final bounding box and grid geometry (grid_geometry).
 __global__ __launch_bounds__(kBlock) void k_grid_setup(const float4 *__restrict__ partial,
                                                        int n_partial, float rn, float cs_req,
                                                        int max_cells, int n,
@@ -88,44 +48,10 @@ __global__ __launch_bounds__(kBlock) void k_grid_setup(const float4 *__restrict_
         b.z = fmaxf(b.z, q.z);
         b.w = fmaxf(b.w, q.w);
     }
-    b = block_bbox(b);
+    b = block_bbox<kBlock>(b);
     if (threadIdx.x != 0) return;
-    // non-finite boxes (NaN/Inf positions) collapse to a single cell
-    const bool finite = isfinite(b.x) && isfinite(b.y) && isfinite(b.z) && isfinite(b.w);
-    const double w = finite ? (double)b.z - (double)b.x : 0.0;
-    const double h = finite ? (double)b.w - (double)b.y : 0.0;
-    double c0 = cs_req > 0.0f ? (double)cs_req : (double)rn;
-    int m = 1;
-    double cs = c0, fx = 0.0, fy = 0.0;
-    for (int it = 0; it < 200; ++it) {
-        m = (int)ceil((double)rn / c0 - 1e-6);
-        if (m < 1) m = 1;
-        cs = fmax(c0, (double)rn / m) * (1.0 + 1e-5);
-        fx = floor(w / cs) + 1.0;
-        fy = floor(h / cs) + 1.0;
-        if (fx * fy <= (double)max_cells) break;
-        c0 *= 1.25;
-    }
-    if (!(fx * fy <= (double)max_cells)) {
-        // unreachable for finite extents below ~1e19 cell sizes: one cell
-        // holding everything is slow but still exact
-        m = 1;
-        fx = 1.0;
-        fy = 1.0;
-        cs = fmax(w, h) + (double)rn + 1.0;
-    }
     GridMeta g;
-    g.x0 = finite ? b.x : 0.0f;
-    g.y0 = finite ? b.y : 0.0f;
-    g.cs = (float)cs;
-    g.rn = rn;
-    g.nx = (int)fx;
-    g.ny = (int)fy;
-    g.m = m;
-    g.n_cells = g.nx * g.ny;
-    g.cs_d = cs;
-    g.inv_cs = 1.0 / cs;
-    g.rn2 = (double)rn * (double)rn;
+    grid_geometry(b, rn, cs_req, max_cells, g);
     g.cell_base = 0;
     g.agent_base = 0;
     g.n = n;
@@ -285,11 +211,19 @@ hipError_t launch_grid_build(const orca_agents_in &in, int n, const orca_params 
                        p.neighbor_dist, p.cell_size, count_len, n, w.meta);
     hipLaunchKernelGGL(k_cell_count, dim3(nb), dim3(kBlock), 0, stream, in.px, in.py, n, w.meta,
                        w.cell, w.rank, w.count);
+    return launch_scan_scatter(in, n, L, w, w.meta, stream);
+}
+
+hipError_t launch_scan_scatter(const orca_agents_in &in, int n, const Layout &L, const Work &w,
+                               const GridMeta *scan_meta, hipStream_t stream)
+{
+    const int nb = (int)((n + kBlock - 1) / kBlock);
     const int nt = (int)L.n_tiles;
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nt), dim3(kBlock), 0, stream, w.count, w.meta, w.tiles);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kBlock), 0, stream, w.tiles, w.meta);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(kBlock), 0, stream, w.count, w.tiles, w.meta,
-                       w.start);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nt), dim3(kBlock), 0, stream, w.count, scan_meta,
+                       w.tiles);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kBlock), 0, stream, w.tiles, scan_meta);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(kBlock), 0, stream, w.count, w.tiles,
+                       scan_meta, w.start);
     hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, stream, in, n, w.cell, w.rank,
                        w.start, w.s0, w.s1);
     return hipGetLastError();

@@ -1,0 +1,563 @@
+// Per-agent device code of the ORCA step (gfx950), shared by the single-scene
+// and the batched kernels.  One lane per agent:
+//
+//   kNN      exact k nearest (squared distance in FP64 without contraction,
+//            ties by caller index) over the rows of the cell stencil, each row
+//            one contiguous range of the cell-ordered copy
+//   ORCA     one half-plane per neighbour (Fig. 1(b,c), Sec. 3.1), computed
+//            without divergent branches: the arc, leg and overlap forms are
+//            all evaluated and selected, so pedestrians and vehicles run the
+//            same instructions (Sec. 3.1)
+//   LP2      incremental closest-point LP over the half-planes and the speed
+//            disc (Sec. 3)
+//   LP3      least-penetration fallback when LP2 is infeasible (Sec. 3)
+//   update   v' = LP result, p' = p + v' dt, written in caller order
+//
+// The half-planes of a lane live in LDS, one column per lane
+// ([k][block] float4 = (q.x, q.y, d.x, d.y)), so the rolled LP loops index
+// them dynamically without scratch memory.  Header-only: every translation
+// unit instantiates the templates it launches.
+#pragma once
+
+#include "orca_internal.h"
+
+#include <limits.h>
+#include <math.h>
+
+namespace orca {
+namespace dev {
+
+__device__ __forceinline__ float det2(float ax, float ay, float bx, float by)
+{
+    return ax * by - ay * bx;
+}
+
+// Squared distance in double from FP32 positions, each operation rounded
+// separately (no fused multiply-add): the neighbour order is defined on it.
+__device__ __forceinline__ double nb_key(float xi, float yi, float xj, float yj)
+{
+#pragma clang fp contract(off)
+    const double dx = (double)xj - (double)xi;
+    const double dy = (double)yj - (double)yi;
+    return dx * dx + dy * dy;
+}
+
+// ---------------------------------------------------------------------------
+// Exact k-nearest selection.
+//
+// Candidates are taken row by row from the cell stencil; each row is clipped
+// to the chord of the neighbour circle at the row's nearest y (FP64, with a
+// margin of 1e-6 cell on every bound, far above the rounding of the cell
+// coordinates), so every agent with key < R_n^2 is visited.
+//
+// Pass 1 counts the in-range candidates of the lane in kBins bins of equal
+// area (bin = floor(key * kBins / R_n^2), monotone in the key); the counts
+// are 8-bit fields of two 64-bit registers.  The first bin b* at which the
+// running count reaches k is the threshold: every candidate of a lower bin is
+// among the k nearest and the rest of the k nearest lie in bin b*.
+// Pass 2 scatters the candidates of bins <= b* into the lane's LDS column in
+// bin order (bucket offsets are 8-bit fields too), and an insertion pass
+// orders each bucket.  Buffer entries are (float(key) bits << 32 | cell-order
+// position): a strict order of the FP32-rounded keys implies the same order
+// of the FP64 keys (rounding is monotone); equal FP32 keys are resolved by
+// recomputing the FP64 keys and then the caller indices.
+// A lane whose counts could overflow (> 255 in range) or whose buckets do
+// not fit the buffer selects by repeated minimum instead (exact, slower).
+// ---------------------------------------------------------------------------
+constexpr int kBins = 16;
+
+template <int K>
+struct KnnShape {
+    static constexpr int kSlots = K < 8 ? 8 : K;  // 16-byte LDS slots per lane
+    static constexpr int kCap = 2 * kSlots;       // buffer entries per lane
+};
+
+// Entry e of lane `tid` inside a [slot][BLOCK] float4 array viewed as u64.
+template <int BLOCK>
+__device__ __forceinline__ int buf_idx(int e, int tid)
+{
+    return (e >> 1) * (2 * BLOCK) + 2 * tid + (e & 1);
+}
+
+__device__ __forceinline__ uint64_t pack_entry(double key, uint32_t t)
+{
+    return ((uint64_t)__float_as_uint((float)key) << 32) | (uint64_t)t;
+}
+
+// Strict (key, caller index) order of two buffer entries.
+__device__ __forceinline__ bool entry_less(uint64_t ea, uint64_t eb, const float4 *__restrict__ s0,
+                                           float xi, float yi)
+{
+    const uint32_t ha = (uint32_t)(ea >> 32), hb = (uint32_t)(eb >> 32);
+    if (ha != hb) return ha < hb;
+    const float4 ca = s0[(uint32_t)ea];
+    const float4 cb = s0[(uint32_t)eb];
+    const double ka = nb_key(xi, yi, ca.x, ca.y);
+    const double kb = nb_key(xi, yi, cb.x, cb.y);
+    if (ka != kb) return ka < kb;
+    return __float_as_int(ca.z) < __float_as_int(cb.z);
+}
+
+// Visits the cell-order candidates [ra, rb) in order, keeping four
+// independent loads in flight per lane.
+template <class F>
+__device__ __forceinline__ void scan_range(const float4 *__restrict__ s0, uint32_t ra, uint32_t rb,
+                                           F &&visit)
+{
+    uint32_t t = ra;
+    for (; t + 4 <= rb; t += 4) {
+        const float4 c0 = s0[t], c1 = s0[t + 1], c2 = s0[t + 2], c3 = s0[t + 3];
+        visit(c0, t);
+        visit(c1, t + 1);
+        visit(c2, t + 2);
+        visit(c3, t + 3);
+    }
+    for (; t < rb; ++t) visit(s0[t], t);
+}
+
+// Grid rows that can hold an agent within R_n of y.
+__device__ __forceinline__ void row_span(const GridMeta &g, double yd, int &ya, int &yb)
+{
+    const double rn = sqrt(g.rn2);
+    const double ua = floor((yd - rn - (double)g.y0) * g.inv_cs - 1e-6);
+    const double ub = floor((yd + rn - (double)g.y0) * g.inv_cs + 1e-6);
+    ya = (int)fmin(fmax(ua, 0.0), (double)(g.ny - 1));
+    yb = (int)fmin(fmax(ub, 0.0), (double)(g.ny - 1));
+}
+
+// Cell-order range of row yy clipped to the chord; false when empty.
+__device__ __forceinline__ bool row_range(const GridMeta &g, const uint32_t *__restrict__ start,
+                                          double xd, double yd, int yy, uint32_t &a, uint32_t &b)
+{
+    const double ylo = (double)g.y0 + (double)yy * g.cs_d;
+    const double dy = fmax(fmax(ylo - yd, yd - (ylo + g.cs_d)) - 1e-6 * g.cs_d, 0.0);
+    const double h2 = g.rn2 - dy * dy;
+    if (!(h2 > 0.0)) return false;
+    const double hw = sqrt(h2);
+    const double ua = floor((xd - hw - (double)g.x0) * g.inv_cs - 1e-6);
+    const double ub = floor((xd + hw - (double)g.x0) * g.inv_cs + 1e-6);
+    const int xa = (int)fmin(fmax(ua, 0.0), (double)(g.nx - 1));
+    const int xb = (int)fmin(fmax(ub, 0.0), (double)(g.nx - 1));
+    const int row = g.cell_base + yy * g.nx;
+    a = start[row + xa];
+    b = start[row + xb + 1];
+    if (b > g.seg_end) b = g.seg_end;  // defensive: stay inside the scene
+    return a < b;
+}
+
+// Selects the (at most K) nearest agents of the lane into entries [0, m) of
+// its LDS buffer, ascending; returns m.
+template <int K, int BLOCK>
+__device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
+                          const float4 *__restrict__ s0, float xi, float yi, int self,
+                          uint64_t *buf, int tid)
+{
+    constexpr int kCap = KnnShape<K>::kCap;
+    const double xd = xi, yd = yi;
+    const double bscale = (double)kBins / g.rn2;
+    int ya, yb;
+    row_span(g, yd, ya, yb);
+
+    // pass 1: per-bin counts
+    uint64_t hlo = 0, hhi = 0;
+    uint32_t total = 0;
+    for (int yy = ya; yy <= yb; ++yy) {
+        uint32_t ra, rb;
+        if (!row_range(g, start, xd, yd, yy, ra, rb)) continue;
+        scan_range(s0, ra, rb, [&](const float4 &c, uint32_t) {
+            const double key = nb_key(xi, yi, c.x, c.y);
+            if (key < g.rn2 && __float_as_int(c.z) != self) {
+                const int bin = min((int)(key * bscale), kBins - 1);
+                const uint64_t inc = 1ull << ((bin & 7) * 8);
+                hlo += bin < 8 ? inc : 0ull;
+                hhi += bin < 8 ? 0ull : inc;
+                ++total;
+            }
+        });
+    }
+
+    // threshold bin and bucket offsets
+    uint64_t olo = 0, ohi = 0;
+    uint32_t cum = 0, take = 0;
+    int bstar = kBins - 1;
+    bool found = false;
+#pragma unroll
+    for (int b = 0; b < kBins; ++b) {
+        const uint32_t cnt = (uint32_t)(((b < 8 ? hlo : hhi) >> ((b & 7) * 8)) & 0xffull);
+        if (b < 8)
+            olo |= (uint64_t)(cum & 0xffu) << (b * 8);
+        else
+            ohi |= (uint64_t)(cum & 0xffu) << ((b - 8) * 8);
+        cum += cnt;
+        if (!found && cum >= (uint32_t)K) {
+            found = true;
+            bstar = b;
+            take = cum;
+        }
+    }
+    if (!found) take = total;
+
+    if (total <= 255u && take <= (uint32_t)kCap) {
+        // pass 2: bucket scatter of bins <= b*
+        for (int yy = ya; yy <= yb; ++yy) {
+            uint32_t ra, rb;
+            if (!row_range(g, start, xd, yd, yy, ra, rb)) continue;
+            scan_range(s0, ra, rb, [&](const float4 &c, uint32_t t) {
+                const double key = nb_key(xi, yi, c.x, c.y);
+                if (key < g.rn2 && __float_as_int(c.z) != self) {
+                    const int bin = min((int)(key * bscale), kBins - 1);
+                    if (bin <= bstar) {
+                        const int sh = (bin & 7) * 8;
+                        const uint32_t slot = (uint32_t)(((bin < 8 ? olo : ohi) >> sh) & 0xffull);
+                        const uint64_t inc = 1ull << sh;
+                        olo += bin < 8 ? inc : 0ull;
+                        ohi += bin < 8 ? 0ull : inc;
+                        if (slot < (uint32_t)kCap)  // always true: both passes count alike
+                            buf[buf_idx<BLOCK>((int)slot, tid)] = pack_entry(key, t);
+                    }
+                }
+            });
+        }
+        // order inside the buckets (bins are already in order)
+        for (int p = 1; p < (int)take; ++p) {
+            const uint64_t e = buf[buf_idx<BLOCK>(p, tid)];
+            int q = p - 1;
+            while (q >= 0) {
+                const uint64_t f = buf[buf_idx<BLOCK>(q, tid)];
+                if (!entry_less(e, f, s0, xi, yi)) break;
+                buf[buf_idx<BLOCK>(q + 1, tid)] = f;
+                --q;
+            }
+            buf[buf_idx<BLOCK>(q + 1, tid)] = e;
+        }
+        return take < (uint32_t)K ? (int)take : K;
+    }
+
+    // fallback: repeated minimum over all candidates, strictly above the last pick
+    double lk = -1.0;
+    int lj = -1;
+    int m = 0;
+    for (; m < K; ++m) {
+        double bk = INFINITY;
+        int bj = INT_MAX;
+        uint32_t bt = 0;
+        for (int yy = ya; yy <= yb; ++yy) {
+            uint32_t ra, rb;
+            if (!row_range(g, start, xd, yd, yy, ra, rb)) continue;
+            for (uint32_t t = ra; t < rb; ++t) {
+                const float4 c = s0[t];
+                const int j = __float_as_int(c.z);
+                const double key = nb_key(xi, yi, c.x, c.y);
+                const bool above = key > lk || (key == lk && j > lj);
+                const bool below = key < bk || (key == bk && j < bj);
+                if (key < g.rn2 && j != self && above && below) {
+                    bk = key;
+                    bj = j;
+                    bt = t;
+                }
+            }
+        }
+        if (bj == INT_MAX) break;
+        buf[buf_idx<BLOCK>(m, tid)] = pack_entry(bk, bt);
+        lk = bk;
+        lj = bj;
+    }
+    return m;
+}
+
+// ORCA_{A|B} as (q.x, q.y, d.x, d.y); permitted side det(d, v - q) >= 0.
+// P = p_B - p_A, V = v_A - v_B, R = r_A + r_B.
+//  - not overlapping: w = V - P/tau; the cutoff arc is nearest when the angle
+//    between w and -P is below arccos(R/|P|), else the left leg (det(P,w) > 0)
+//    or the right leg; u is the shortest vector from V to the boundary and n
+//    the outward normal there.
+//  - overlapping (|P| <= R): the horizon becomes dt and only the disc is used;
+//    w = 0 takes the normal (+1, 0) if A's caller index is the smaller one,
+//    else (-1, 0).
+//  - q = v_A + f u, d = (n.y, -n.x).  q is kept as this sum: with f = 0 all
+//    of an agent's lines then pass exactly through v_A, so a feasible set that
+//    has shrunk to that single point stays feasible in FP32.
+__device__ __forceinline__ float4 halfplane(float pax, float pay, float vax, float vay, float ra,
+                                            float pbx, float pby, float vbx, float vby, float rb,
+                                            float f, float inv_tau, float inv_dt, bool a_first)
+{
+    const float Px = pbx - pax, Py = pby - pay;
+    const float Vx = vax - vbx, Vy = vay - vby;
+    const float R = ra + rb;
+    const float dist2 = Px * Px + Py * Py;
+    const float R2 = R * R;
+    const bool overlap = !(dist2 > R2);
+    const float it = overlap ? inv_dt : inv_tau;
+    const float wx = Vx - Px * it, wy = Vy - Py * it;
+    const float w2 = wx * wx + wy * wy;
+    const float wp = wx * Px + wy * Py;
+    const bool arc = overlap || (wp < 0.0f && wp * wp > R2 * w2);
+    // disc (cutoff arc / overlap) form
+    const bool wz = !(w2 > 0.0f);
+    const float wl = sqrtf(w2);
+    const float iwl = wz ? 0.0f : 1.0f / wl;
+    const float anx = wz ? (a_first ? 1.0f : -1.0f) : wx * iwl;
+    const float any = wz ? 0.0f : wy * iwl;
+    const float ul = R * it - wl;
+    // leg form
+    const float leg = sqrtf(fmaxf(dist2 - R2, 0.0f));
+    const float id2 = overlap ? 0.0f : 1.0f / dist2;
+    const bool left = det2(Px, Py, wx, wy) > 0.0f;
+    const float sR = left ? R : -R;
+    const float ex = (Px * leg - Py * sR) * id2;
+    const float ey = (Px * sR + Py * leg) * id2;
+    const float lnx = left ? -ey : ey;
+    const float lny = left ? ex : -ex;
+    const float s = Vx * ex + Vy * ey;
+    const float nx = arc ? anx : lnx;
+    const float ny = arc ? any : lny;
+    const float ux = arc ? ul * anx : s * ex - Vx;
+    const float uy = arc ? ul * any : s * ey - Vy;
+    return make_float4(vax + f * ux, vay + f * uy, ny, -nx);
+}
+
+// Half-planes of this lane, stored in LDS column `tid`.
+template <int BLOCK>
+struct LdsLines {
+    const float4 *L;
+    int tid;
+    __device__ __forceinline__ bool get(int j, float4 &l) const
+    {
+        l = L[j * BLOCK + tid];
+        return true;
+    }
+};
+
+// Boundaries of "delta_j(v) <= delta_i(v)" for j < i (least-penetration
+// sub-problem), recomputed on demand from lines i and j.  Lines parallel to i
+// and pointing the same way are not constraints (invalid).
+// Since delta_j(v) - delta_i(v) = c - det(e, v) with e = d_j - d_i and
+// c = det(d_j, q_j) - det(d_i, q_i), the boundary is det(e/|e|, v) = c/|e|;
+// it is stored through its point nearest the origin, (c/|e|) (-e_y, e_x)/|e|.
+// This is the same line as the one through the intersection of lines i and j
+// (or the midpoint of q_i, q_j for antiparallel lines), but stays well
+// scaled in FP32 when the two lines are nearly parallel and intersect far
+// away from the speed disc.
+template <int BLOCK>
+struct ProjLines {
+    const float4 *L;
+    int tid;
+    float4 li;
+    float ci;    // det(d_i, q_i)
+    float eps;
+    __device__ __forceinline__ bool get(int j, float4 &out) const
+    {
+        const float4 lj = L[j * BLOCK + tid];
+        const float dij = det2(li.z, li.w, lj.z, lj.w);
+        if (fabsf(dij) <= eps && li.z * lj.z + li.w * lj.w > 0.0f) return false;
+        const float ex = lj.z - li.z, ey = lj.w - li.w;
+        const float il = 1.0f / sqrtf(ex * ex + ey * ey);
+        const float dx = ex * il, dy = ey * il;
+        const float off = (det2(lj.z, lj.w, lj.x, lj.y) - ci) * il;
+        out = make_float4(-dy * off, dx * off, dx, dy);
+        return true;
+    }
+};
+
+// One-dimensional sub-problem on line li (index i): the parameter interval
+// inside the speed disc and on the permitted side of every valid line j < i.
+// mode 0: closest point to (ox, oy); mode 1: extreme along unit (ox, oy), or,
+// when the line is orthogonal to it, the point closest to (tx, ty).
+template <class Src>
+__device__ __forceinline__ bool lp1(const Src &src, int i, float4 li, float vmax, int mode,
+                                    float ox, float oy, float tx, float ty, float eps, float &x,
+                                    float &y)
+{
+    const float dot = li.x * li.z + li.y * li.w;
+    const float disc = dot * dot + vmax * vmax - (li.x * li.x + li.y * li.y);
+    if (disc < 0.0f) return false;
+    const float sq = sqrtf(disc);
+    float tl = -dot - sq, tr = -dot + sq;
+    for (int j = 0; j < i; ++j) {
+        float4 lj;
+        if (!src.get(j, lj)) continue;
+        const float a = det2(lj.z, lj.w, li.z, li.w);
+        const float b = det2(lj.z, lj.w, li.x - lj.x, li.y - lj.y);
+        if (fabsf(a) <= eps) {
+            if (b < 0.0f) return false;
+            continue;
+        }
+        const float t = -b / a;
+        if (a > 0.0f)
+            tl = fmaxf(tl, t);
+        else
+            tr = fminf(tr, t);
+        if (tl > tr) return false;
+    }
+    float t;
+    if (mode == 0) {
+        t = li.z * (ox - li.x) + li.w * (oy - li.y);
+        t = fminf(fmaxf(t, tl), tr);
+    } else {
+        const float sd = ox * li.z + oy * li.w;
+        if (fabsf(sd) <= eps) {
+            t = li.z * (tx - li.x) + li.w * (ty - li.y);
+            t = fminf(fmaxf(t, tl), tr);
+        } else {
+            t = sd > 0.0f ? tr : tl;
+        }
+    }
+    x = li.x + t * li.z;
+    y = li.y + t * li.w;
+    return true;
+}
+
+// Incremental 2D LP over lines 0..m-1 of `src` and the disc |v| <= vmax.
+// Returns the first infeasible line, or m; v keeps its pre-failure value.
+template <class Src>
+__device__ __forceinline__ int lp2(const Src &src, int m, float vmax, int mode, float ox,
+                                   float oy, float tx, float ty, float eps, float &vx, float &vy)
+{
+    float x, y;
+    if (mode == 1) {
+        x = ox * vmax;
+        y = oy * vmax;
+    } else {
+        const float o2 = ox * ox + oy * oy;
+        if (o2 > vmax * vmax) {
+            const float sc = vmax / sqrtf(o2);
+            x = ox * sc;
+            y = oy * sc;
+        } else {
+            x = ox;
+            y = oy;
+        }
+    }
+    for (int i = 0; i < m; ++i) {
+        float4 li;
+        if (!src.get(i, li)) continue;
+        if (det2(li.z, li.w, li.x - x, li.y - y) > 0.0f) {
+            float nx = x, ny = y;
+            if (!lp1(src, i, li, vmax, mode, ox, oy, tx, ty, eps, nx, ny)) {
+                vx = x;
+                vy = y;
+                return i;
+            }
+            x = nx;
+            y = ny;
+        }
+    }
+    vx = x;
+    vy = y;
+    return m;
+}
+
+// Least penetration (Sec. 3): from LP2's partial result at line `fail`, each
+// later line i whose penetration exceeds the current level re-solves v in the
+// region where no earlier line penetrates more than line i, as deep into line
+// i's permitted side as possible.
+template <int BLOCK>
+__device__ __forceinline__ void lp3(const float4 *L, int tid, int m, int fail, float vmax,
+                                    float tx, float ty, float eps, float &vx, float &vy)
+{
+    float level = 0.0f;
+    float x = vx, y = vy;
+    for (int i = fail; i < m; ++i) {
+        const float4 li = L[i * BLOCK + tid];
+        if (det2(li.z, li.w, li.x - x, li.y - y) <= level) continue;
+        ProjLines<BLOCK> src{L, tid, li, det2(li.z, li.w, li.x, li.y), eps};
+        float nx = x, ny = y;
+        if (lp2(src, i, vmax, 1, -li.w, li.z, tx, ty, eps, nx, ny) == i) {
+            x = nx;
+            y = ny;
+        }
+        level = det2(li.z, li.w, li.x - x, li.y - y);
+    }
+    vx = x;
+    vy = y;
+}
+
+// Scalar parameters of the scene an agent belongs to, in the form the
+// per-agent step uses.
+struct SceneP {
+    float dt, inv_dt, inv_tau, eps;
+    int k;
+    int pref_is_goal;
+    float f00, f01, f10, f11;
+};
+
+__device__ __host__ __forceinline__ SceneP scene_params(const orca_params &p)
+{
+    SceneP s;
+    s.dt = p.dt;
+    s.inv_dt = 1.0f / p.dt;
+    s.inv_tau = 1.0f / p.time_horizon;
+    s.eps = p.par_eps;
+    s.k = p.max_neighbors;
+    s.pref_is_goal = p.pref_is_goal;
+    s.f00 = p.f[0][0];
+    s.f01 = p.f[0][1];
+    s.f10 = p.f[1][0];
+    s.f11 = p.f[1][1];
+    return s;
+}
+
+// One whole ORCA step of the agent at cell-order position s: neighbours,
+// half-planes (into the lane's LDS column), LP2, LP3 if needed, update.
+// `lines` is a [max(K, 8)][BLOCK] float4 array; lane `tid` owns column tid.
+template <int K, int BLOCK>
+__device__ __forceinline__ void step_agent(int s, const GridMeta &g, const SceneP &p,
+                                           const orca_agents_in &in, const orca_agents_out &out,
+                                           const uint32_t *__restrict__ start,
+                                           const float4 *__restrict__ s0,
+                                           const float4 *__restrict__ s1, float4 *lines, int tid)
+{
+    const float4 me0 = s0[s];
+    const float4 me1 = s1[s];
+    const int i = __float_as_int(me0.z);
+    const float xi = me0.x, yi = me0.y, ri = me0.w, vxi = me1.x, vyi = me1.y;
+    const int ci = __float_as_int(me1.z) & 1;
+
+    uint64_t *buf = reinterpret_cast<uint64_t *>(lines);
+    const int found = knn_select<K, BLOCK>(g, start, s0, xi, yi, i, buf, tid);
+    const int kk = p.k < K ? p.k : K;
+    const int m = found < kk ? found : kk;
+    uint32_t pos[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) pos[q] = q < m ? (uint32_t)buf[buf_idx<BLOCK>(q, tid)] : 0u;
+
+    const float fa = ci ? p.f10 : p.f00;  // f[ci][0]
+    const float fb = ci ? p.f11 : p.f01;  // f[ci][1]
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        if (q < m) {
+            const float4 b0 = s0[pos[q]];
+            const float4 b1 = s1[pos[q]];
+            const float f = (__float_as_int(b1.z) & 1) ? fb : fa;
+            lines[q * BLOCK + tid] = halfplane(xi, yi, vxi, vyi, ri, b0.x, b0.y, b1.x, b1.y, b0.w,
+                                               f, p.inv_tau, p.inv_dt, i < __float_as_int(b0.z));
+        }
+    }
+
+    const float vmax = in.max_speed[i];
+    float prx = in.pref_x[i], pry = in.pref_y[i];
+    if (p.pref_is_goal) {
+        const float gx = prx - xi, gy = pry - yi;
+        const float d2 = gx * gx + gy * gy;
+        const float sc = d2 > 0.0f ? fminf(vmax / sqrtf(d2), p.inv_dt) : 0.0f;
+        prx = gx * sc;
+        pry = gy * sc;
+    }
+
+    LdsLines<BLOCK> src{lines, tid};
+    float vx, vy;
+    const int fail = lp2(src, m, vmax, 0, prx, pry, 0.0f, 0.0f, p.eps, vx, vy);
+    uint8_t st = 0;
+    if (fail < m) {
+        lp3<BLOCK>(lines, tid, m, fail, vmax, prx, pry, p.eps, vx, vy);
+        st = 1;
+    }
+    out.vx[i] = vx;
+    out.vy[i] = vy;
+    out.px[i] = xi + vx * p.dt;
+    out.py[i] = yi + vy * p.dt;
+    if (out.status) out.status[i] = st;
+}
+
+}  // namespace dev
+}  // namespace orca

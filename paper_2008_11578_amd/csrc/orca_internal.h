@@ -33,9 +33,12 @@ struct GridMeta {
 
 // Byte offsets of the workspace regions (all 256-byte aligned).
 struct Layout {
-    size_t meta, partial, cell, rank, count, start, tiles, s0, s1, total;
+    size_t meta, partial, queue, cell, rank, count, start, tiles, s0, s1, total;
     int64_t n, n_scenes, max_cells, n_tiles;
 };
+
+// Cells of the batched form: 2 per agent + 64 per scene.
+__host__ __device__ inline int64_t batched_cells(int64_t n, int64_t n_scenes) { return 2 * n + 64 * n_scenes; }
 
 // Cell coordinate along one axis, in FP64, clamped to [0, ncell - 1]
 // (fmax/fmin also map NaN to 0).  Shared by the grid build and the
@@ -59,6 +62,90 @@ __device__ __forceinline__ int xcd_tile(int b, int nb)
     return x * q + (x < r ? x : r) + b / kXcds;
 }
 
+__device__ __forceinline__ float wave_min(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+__device__ __forceinline__ float wave_max(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// Block-wide (min x, min y, max x, max y).  Result valid in thread 0.
+template <int kBlock>
+__device__ float4 block_bbox(float4 b)
+{
+    __shared__ float4 red[kBlock / kWave];
+    b.x = wave_min(b.x);
+    b.y = wave_min(b.y);
+    b.z = wave_max(b.z);
+    b.w = wave_max(b.w);
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    if (lane == 0) red[wid] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < kBlock / kWave; ++k) {
+            b.x = fminf(b.x, red[k].x);
+            b.y = fminf(b.y, red[k].y);
+            b.z = fmaxf(b.z, red[k].z);
+            b.w = fmaxf(b.w, red[k].w);
+        }
+    }
+    return b;
+}
+
+// Grid geometry of one scene from its bounding box b = (min x, min y,
+// max x, max y):
+//   m  = stencil radius in cells, ceil(R_n / requested cell size)
+//   cs = max(requested, R_n / m) * (1 + 1e-5), so that m * cs > R_n with a
+//        margin far above the rounding of the FP64 cell coordinates
+//   the cell size grows (and m is re-derived) until nx * ny <= max_cells;
+//   non-finite boxes (NaN/Inf positions) collapse to a single cell.
+// Fills every field except cell_base, agent_base, n and seg_end.
+__device__ __forceinline__ void grid_geometry(float4 b, float rn, float cs_req, int max_cells,
+                                              GridMeta &g)
+{
+    const bool finite = isfinite(b.x) && isfinite(b.y) && isfinite(b.z) && isfinite(b.w);
+    const double w = finite ? (double)b.z - (double)b.x : 0.0;
+    const double h = finite ? (double)b.w - (double)b.y : 0.0;
+    double c0 = cs_req > 0.0f ? (double)cs_req : (double)rn;
+    int m = 1;
+    double cs = c0, fx = 0.0, fy = 0.0;
+    for (int it = 0; it < 200; ++it) {
+        m = (int)ceil((double)rn / c0 - 1e-6);
+        if (m < 1) m = 1;
+        cs = fmax(c0, (double)rn / m) * (1.0 + 1e-5);
+        fx = floor(w / cs) + 1.0;
+        fy = floor(h / cs) + 1.0;
+        if (fx * fy <= (double)max_cells) break;
+        c0 *= 1.25;
+    }
+    if (!(fx * fy <= (double)max_cells) || !(cs > 0.0)) {
+        // only for extents beyond ~1e19 cells or non-positive sizes: one
+        // cell holding everything is slow but still exact
+        m = 1;
+        fx = 1.0;
+        fy = 1.0;
+        cs = fmax(w, h) + fabs((double)rn) + 1.0;
+    }
+    g.x0 = finite ? b.x : 0.0f;
+    g.y0 = finite ? b.y : 0.0f;
+    g.cs = (float)cs;
+    g.rn = rn;
+    g.nx = (int)fx;
+    g.ny = (int)fy;
+    g.m = m;
+    g.n_cells = g.nx * g.ny;
+    g.cs_d = cs;
+    g.inv_cs = 1.0 / cs;
+    g.rn2 = (double)rn * (double)rn;
+}
+
 Layout make_layout(int64_t n, int64_t n_scenes, int64_t max_cells);
 
 inline int64_t default_max_cells(int64_t n) { return n * 2 > 4096 ? n * 2 : 4096; }
@@ -67,6 +154,7 @@ inline int64_t default_max_cells(int64_t n) { return n * 2 > 4096 ? n * 2 : 4096
 struct Work {
     GridMeta *meta;
     float4 *partial;
+    uint32_t *queue;   // 8 tile counters (one per XCD) of the persistent kernel
     uint32_t *cell;
     uint32_t *rank;
     uint32_t *count;
@@ -82,6 +170,18 @@ Work bind(const Layout &L, void *ws);
 // gather into cell order.  Returns hipSuccess or the launch error.
 hipError_t launch_grid_build(const orca_agents_in &in, int n, const orca_params &p,
                              const Layout &L, const Work &w, hipStream_t stream);
+
+// Histogram scan and scatter into cell order; scan_meta supplies the number
+// of cells (n_cells) and of agents (n) of the whole cell space.
+hipError_t launch_scan_scatter(const orca_agents_in &in, int n, const Layout &L, const Work &w,
+                               const GridMeta *scan_meta, hipStream_t stream);
+
+// Batched form: many independent scenes, scene s owning caller indices
+// [off[s], off[s+1]) and cells [2 off[s] + 64 s, 2 off[s+1] + 64 (s + 1)).
+hipError_t launch_batched(const orca_agents_in &in, const orca_agents_out &out, int n,
+                          const int32_t *scene_off, int n_scenes, const orca_params *params,
+                          int k_max, const Layout &L, const Work &w, int32_t *error_flag,
+                          int mode, hipStream_t stream);
 
 // Fused neighbour search + half-planes + LP + update for one scene.
 hipError_t launch_step(const orca_agents_in &in, const orca_agents_out &out, int n,

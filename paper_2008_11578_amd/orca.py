@@ -45,6 +45,12 @@ class AgentsOut(ctypes.Structure):
     _fields_ = [(k, ctypes.c_void_p) for k in ("px", "py", "vx", "vy", "status")]
 
 
+class OrcaBatch(ctypes.Structure):
+    _fields_ = [("scene_off", ctypes.c_void_p), ("n_scenes", ctypes.c_int32),
+                ("params", ctypes.c_void_p), ("max_neighbors", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("error_flag", ctypes.c_void_p)]
+
+
 class StepEvents(ctypes.Structure):
     _fields_ = [("grid_begin", ctypes.c_void_p), ("step_begin", ctypes.c_void_p),
                 ("step_end", ctypes.c_void_p)]
@@ -77,6 +83,9 @@ def lib() -> ctypes.CDLL:
         L.orca_step_ex.argtypes = [ctypes.POINTER(AgentsIn), ctypes.POINTER(AgentsOut), i32,
                                    ctypes.POINTER(OrcaParams), vp, sz,
                                    ctypes.POINTER(StepEvents), vp]
+        L.orca_step_batched.restype = ctypes.c_int
+        L.orca_step_batched.argtypes = [ctypes.POINTER(AgentsIn), ctypes.POINTER(AgentsOut), i32,
+                                        ctypes.POINTER(OrcaBatch), vp, sz, vp]
         L.orca_status_string.restype = ctypes.c_char_p
         L.orca_status_string.argtypes = [ctypes.c_int]
         L.orca_version.restype = ctypes.c_char_p
@@ -232,3 +241,46 @@ def step(state: State, params, ws: Workspace, out: Optional[State] = None,
 
 def params_of(sc: "scenarios.Scenario"):
     return sc.params
+
+
+class Batch:
+    """Scene offsets, per-scene parameters and the error flag of a batch, on
+    the device (``orca_batch``)."""
+
+    def __init__(self, scene_off, scene_params, device="cuda", mode: int = 0):
+        import numpy as np
+        off = np.ascontiguousarray(np.asarray(scene_off), dtype=np.int32)
+        self.n_scenes = int(off.shape[0] - 1)
+        if self.n_scenes < 1 or len(scene_params) != self.n_scenes:
+            raise ValueError("scene_off needs n_scenes + 1 entries and one Params per scene")
+        self.off = torch.as_tensor(off).to(device)
+        arr = (OrcaParams * self.n_scenes)(*[make_params(p) for p in scene_params])
+        raw = np.frombuffer(bytes(arr), dtype=np.uint8).copy()
+        self.params = torch.as_tensor(raw).to(device)
+        self.max_neighbors = max(int(make_params(p).max_neighbors) for p in scene_params)
+        self.mode = int(mode)
+        self.error = torch.zeros(1, dtype=torch.int32, device=device)
+
+    def c_struct(self) -> OrcaBatch:
+        return OrcaBatch(_ptr(self.off), self.n_scenes, _ptr(self.params), self.max_neighbors,
+                         self.mode, _ptr(self.error))
+
+
+def step_batched(state: State, batch: Batch, ws: Workspace, out: Optional[State] = None,
+                 status: Optional[torch.Tensor] = None, stream=None) -> State:
+    """One ORCA step of every scene of the batch (``orca_step_batched``)."""
+    n = state.n
+    if out is None:
+        out = state.clone()
+    if status is not None:
+        _check(status, "status", torch.uint8, n)
+    for k in ("px", "py", "vx", "vy"):
+        _check(getattr(out, k), "out." + k, torch.float32, n)
+    ain = state.agents_in()
+    aout = AgentsOut(_ptr(out.px), _ptr(out.py), _ptr(out.vx), _ptr(out.vy), _ptr(status))
+    b = batch.c_struct()
+    rc = lib().orca_step_batched(ctypes.byref(ain), ctypes.byref(aout), n, ctypes.byref(b),
+                                 ws.ptr(), ws.nbytes, _stream_handle(stream))
+    if rc != ORCA_OK:
+        raise OrcaError("orca_step_batched", rc)
+    return out

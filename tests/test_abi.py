@@ -1,0 +1,141 @@
+"""The C ABI on the CPU: liborca.so loads, exports every function that
+include/orca.h declares, and rejects bad arguments on the host before any
+launch (no GPU needed: none of these calls reaches a kernel)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def orca_mod():
+    from paper_2008_11578_amd import build, orca
+    build.build(force=False)
+    orca.lib()
+    return orca
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "orca.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(orca_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(orca_mod):
+    names = declared_functions()
+    assert {"orca_step", "orca_build_grid", "orca_step_batched", "orca_workspace_bytes"} <= set(names)
+    lib = orca_mod.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_struct_sizes_match_header(orca_mod):
+    assert ctypes.sizeof(orca_mod.OrcaParams) == 4 * 4 + 4 + 4 + 16 + 4
+    assert ctypes.sizeof(orca_mod.AgentsIn) == 9 * 8
+    assert ctypes.sizeof(orca_mod.AgentsOut) == 5 * 8
+    assert ctypes.sizeof(orca_mod.OrcaBatch) == 8 + 4 + 4 + 8 + 4 + 4 + 8
+
+
+def test_status_strings(orca_mod):
+    assert orca_mod.status_string(0) == "ok"
+    assert "invalid" in orca_mod.status_string(-1)
+    assert "workspace" in orca_mod.status_string(-2)
+    assert orca_mod.status_string(12345) == "unknown status"
+    assert "gfx950" in orca_mod.version()
+
+
+def test_workspace_bytes_monotone(orca_mod):
+    wb = orca_mod.workspace_bytes
+    assert wb(-1) == 0
+    prev = 0
+    for n in (0, 1, 100, 10_000, 1 << 20):
+        v = wb(n)
+        assert v >= prev and v % 256 == 0
+        prev = v
+    assert wb(1000, max_cells=1 << 20) > wb(1000, max_cells=16)
+    assert wb(1000, n_scenes=10) > 0
+
+
+def _params(orca_mod, **kw):
+    d = dict(dt=0.1, time_horizon=2.0, neighbor_dist=5.0, cell_size=0.0, max_neighbors=10,
+             pref_is_goal=1, f=((0.5, 1.0), (0.0, 0.5)), par_eps=1e-5)
+    d.update(kw)
+    return orca_mod.make_params(d)
+
+
+FAKE = 0x1000  # non-null address never dereferenced: validation fails first
+
+
+def _in_fake(orca_mod):
+    return orca_mod.AgentsIn(*([FAKE] * 9))
+
+
+def _out_fake(orca_mod):
+    return orca_mod.AgentsOut(FAKE, FAKE, FAKE, FAKE, None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(max_neighbors=0), -4), (dict(max_neighbors=33), -4), (dict(dt=0.0), -1),
+    (dict(dt=float("nan")), -1), (dict(time_horizon=-1.0), -1), (dict(neighbor_dist=0.0), -1),
+    (dict(cell_size=-1.0), -1), (dict(pref_is_goal=2), -1), (dict(par_eps=-1.0), -1),
+])
+def test_step_rejects_bad_params(orca_mod, kw, code):
+    lib = orca_mod.lib()
+    p = _params(orca_mod, **kw)
+    ain, aout = _in_fake(orca_mod), _out_fake(orca_mod)
+    rc = lib.orca_step(ctypes.byref(ain), ctypes.byref(aout), 100, ctypes.byref(p), FAKE,
+                       1 << 30, None)
+    assert rc == code
+
+
+def test_step_argument_errors(orca_mod):
+    lib = orca_mod.lib()
+    p = _params(orca_mod)
+    ain, aout = _in_fake(orca_mod), _out_fake(orca_mod)
+    # n = 0 is a no-op even with null buffers
+    assert lib.orca_step(None, None, 0, ctypes.byref(p), None, 0, None) == 0
+    assert lib.orca_step(ctypes.byref(ain), ctypes.byref(aout), -1, ctypes.byref(p), FAKE, 1 << 30,
+                         None) == -1
+    assert lib.orca_step(ctypes.byref(ain), ctypes.byref(aout), 10, None, FAKE, 1 << 30, None) == -1
+    # null workspace, null input arrays, null outputs
+    assert lib.orca_step(ctypes.byref(ain), ctypes.byref(aout), 10, ctypes.byref(p), None, 1 << 30,
+                         None) == -1
+    bad_in = orca_mod.AgentsIn(*([FAKE] * 8 + [None]))
+    need = orca_mod.workspace_bytes(10)
+    assert lib.orca_step(ctypes.byref(bad_in), ctypes.byref(aout), 10, ctypes.byref(p), FAKE,
+                         need, None) == -1
+    bad_out = orca_mod.AgentsOut(FAKE, None, FAKE, FAKE, None)
+    assert lib.orca_step(ctypes.byref(ain), ctypes.byref(bad_out), 10, ctypes.byref(p), FAKE,
+                         need, None) == -1
+    # workspace too small
+    assert lib.orca_step(ctypes.byref(ain), ctypes.byref(aout), 10, ctypes.byref(p), FAKE, 64,
+                         None) == -2
+    assert lib.orca_build_grid(ctypes.byref(ain), 10, ctypes.byref(p), FAKE, 64, None, None,
+                               None) == -2
+
+
+def test_batched_argument_errors(orca_mod):
+    lib = orca_mod.lib()
+    ain, aout = _in_fake(orca_mod), _out_fake(orca_mod)
+    B = orca_mod.OrcaBatch
+    good = dict(scene_off=FAKE, n_scenes=2, params=FAKE, max_neighbors=16, mode=0, error_flag=None)
+
+    def call(n=100, ws_bytes=1 << 30, **kw):
+        d = dict(good)
+        d.update(kw)
+        b = B(**d)
+        return lib.orca_step_batched(ctypes.byref(ain), ctypes.byref(aout), n, ctypes.byref(b),
+                                     FAKE, ws_bytes, None)
+
+    assert lib.orca_step_batched(None, None, 0, None, None, 0, None) == -1
+    assert call(n=0) == 0
+    assert call(n_scenes=0) == -1
+    assert call(scene_off=None) == -1
+    assert call(params=None) == -1
+    assert call(max_neighbors=0) == -4
+    assert call(max_neighbors=40) == -4
+    assert call(mode=7) == -1
+    assert call(ws_bytes=1024) == -2
