@@ -1,4 +1,5 @@
-"""FP64 CPU oracle for the ORCA step (ctypes wrapper over ``orca_oracle.c``).
+"""FP64 CPU oracle for the ORCA step and its gradient (ctypes wrapper over
+``orca_oracle.cpp``).
 
 TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU
 baseline of the benchmark may use this package; the library path must not.
@@ -16,7 +17,7 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "orca_oracle.c")
+_SRC = os.path.join(_HERE, "orca_oracle.cpp")
 _LIB = os.path.join(_HERE, "liborca_oracle.so")
 K_MAX = 64
 NWORK = 12
@@ -25,11 +26,11 @@ WORK_FIELDS = ("candidates", "in_range", "neighbors", "lp2_checks", "lp2_solves"
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (FP64, no contraction, OpenMP)."""
+    """Compile the oracle with g++ (FP64, no contraction, OpenMP)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
-                               "-Wall", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fPIC",
+                               "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -61,7 +62,15 @@ def lib():
                                  ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
         L.oracle_step.restype = ctypes.c_int
         L.oracle_step.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 9 + \
-            [ctypes.POINTER(_OParams)] + [ctypes.c_void_p] * 10
+            [ctypes.POINTER(_OParams)] + [ctypes.c_void_p] * 11
+        L.oracle_step_d.restype = ctypes.c_int
+        L.oracle_step_d.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 9 + \
+            [ctypes.POINTER(_OParams)] + [ctypes.c_void_p] * 6
+        for name in ("oracle_step_vjp", "oracle_step_vjp_d"):
+            fn = getattr(L, name)
+            fn.restype = ctypes.c_int
+            fn.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 9 + \
+                [ctypes.POINTER(_OParams)] + [ctypes.c_void_p] * 11
         L.oracle_step_batched.restype = ctypes.c_int
         L.oracle_step_batched.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 10 + \
             [ctypes.c_void_p] + [ctypes.c_void_p] * 6
@@ -155,7 +164,7 @@ def _state_ptrs(state):
 
 
 def step(state, params, want_neighbors: bool = False, want_work: bool = False,
-         want_lines: bool = False):
+         want_lines: bool = False, want_trace: bool = False):
     """One synchronous step from an FP32 state.  Returns FP64 arrays
     px, py, vx, vy, the status byte (1 = least-penetration fallback used),
     and optionally the neighbour lists, per-agent work counters, and each
@@ -172,13 +181,15 @@ def step(state, params, want_neighbors: bool = False, want_work: bool = False,
     pref = np.zeros((n, 2), np.float64) if want_lines else None
     if want_lines and not want_neighbors:
         cnt = np.zeros(n, np.int32)
+    trace = np.zeros(n, np.uint64) if want_trace else None
     rc = lib().oracle_step(n, *ptrs, ctypes.byref(p), out["px"].ctypes.data,
                            out["py"].ctypes.data, out["vx"].ctypes.data, out["vy"].ctypes.data,
                            status.ctypes.data, nbr.ctypes.data if nbr is not None else None,
                            cnt.ctypes.data if cnt is not None else None,
                            work.ctypes.data if work is not None else None,
                            lines.ctypes.data if lines is not None else None,
-                           pref.ctypes.data if pref is not None else None)
+                           pref.ctypes.data if pref is not None else None,
+                           trace.ctypes.data if trace is not None else None)
     if rc != 0:
         raise ValueError(f"oracle_step failed ({rc})")
     out["status"] = status
@@ -191,7 +202,106 @@ def step(state, params, want_neighbors: bool = False, want_work: bool = False,
         out["lines"] = lines
         out["pref"] = pref
         out["cnt"] = cnt
+    if want_trace:
+        out["trace"] = trace
     return out
+
+
+def _d(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data
+
+
+def step_vjp(state, params, g_px1, g_py1, g_vx1, g_vy1, double_state: bool = False):
+    """Vector-Jacobian product of one step at `state` (FP32 arrays, or double
+    arrays with double_state=True).  Returns dict g_px, g_py, g_vx, g_vy (the
+    cotangents of the step-t state), g_pref_x, g_pref_y (of the pref input:
+    desired velocity, or goal in goal mode) and g_tau."""
+    g = state.get if isinstance(state, dict) else (lambda k: getattr(state, k))
+    if double_state:
+        keep = [np.ascontiguousarray(g(k), dtype=np.float64) for k in _STATE]
+    else:
+        keep = [np.ascontiguousarray(g(k), dtype=np.float32) for k in _STATE]
+    cls = np.ascontiguousarray(g("cls"), dtype=np.uint8)
+    n = keep[0].shape[0]
+    p = make_params(params)
+    gin = [_d(x) for x in (g_px1, g_py1, g_vx1, g_vy1)]
+    out = {k: np.zeros(n) for k in ("g_px", "g_py", "g_vx", "g_vy", "g_pref_x", "g_pref_y")}
+    tau = np.zeros(1)
+    fn = lib().oracle_step_vjp_d if double_state else lib().oracle_step_vjp
+    rc = fn(n, *[a.ctypes.data for a in keep], cls.ctypes.data, ctypes.byref(p),
+            *[x[1] for x in gin], out["g_px"].ctypes.data, out["g_py"].ctypes.data,
+            out["g_vx"].ctypes.data, out["g_vy"].ctypes.data, out["g_pref_x"].ctypes.data,
+            out["g_pref_y"].ctypes.data, tau.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"oracle_step_vjp failed ({rc})")
+    out["g_tau"] = float(tau[0])
+    return out
+
+
+def rollout(state, params, steps: int, keep_states: bool = False):
+    """FP64 rollout: `steps` oracle steps carrying the state in double.
+    Returns dict px, py, vx, vy (final), trace (hash of every agent's
+    neighbour lists and branch outcomes over all steps) and, with
+    keep_states, the list of per-step double states (step 0 first)."""
+    g = state.get if isinstance(state, dict) else (lambda k: getattr(state, k))
+    cur = {k: np.ascontiguousarray(g(k), dtype=np.float64) for k in _STATE}
+    cls = np.ascontiguousarray(g("cls"), dtype=np.uint8)
+    n = cur["px"].shape[0]
+    p = make_params(params)
+    hist = []
+    h = np.uint64(1469598103934665603)
+    trace = np.zeros(n, np.uint64)
+    for _ in range(steps):
+        if keep_states:
+            hist.append({k: cur[k].copy() for k in ("px", "py", "vx", "vy")})
+        nxt = {k: np.zeros(n) for k in ("px", "py", "vx", "vy")}
+        rc = lib().oracle_step_d(n, *[cur[k].ctypes.data for k in _STATE], cls.ctypes.data,
+                                 ctypes.byref(p), nxt["px"].ctypes.data, nxt["py"].ctypes.data,
+                                 nxt["vx"].ctypes.data, nxt["vy"].ctypes.data, None,
+                                 trace.ctypes.data)
+        if rc != 0:
+            raise ValueError(f"oracle_step_d failed ({rc})")
+        with np.errstate(over="ignore"):
+            h = np.uint64((int(h) * 1099511628211 + int(np.bitwise_xor.reduce(
+                trace * np.arange(1, n + 1, dtype=np.uint64)))) % (1 << 64))
+        cur.update(nxt)
+    out = {k: cur[k] for k in ("px", "py", "vx", "vy")}
+    out["trace"] = int(h)
+    if keep_states:
+        out["states"] = hist
+    return out
+
+
+def rollout_grad(state, params, steps: int, target_x, target_y):
+    """Loss L = mean_i |p_i(T) - target_i|^2 of an FP64 rollout and its
+    gradient with respect to every agent's pref input and tau, by chaining
+    the oracle's one-step VJPs backwards along the stored trajectory."""
+    g = state.get if isinstance(state, dict) else (lambda k: getattr(state, k))
+    base = {k: np.ascontiguousarray(g(k), dtype=np.float64) for k in _STATE}
+    cls = np.ascontiguousarray(g("cls"), dtype=np.uint8)
+    n = base["px"].shape[0]
+    fw = rollout(dict(base, cls=cls), params, steps, keep_states=True)
+    tx = np.asarray(target_x, np.float64)
+    ty = np.asarray(target_y, np.float64)
+    loss = float(np.mean((fw["px"] - tx) ** 2 + (fw["py"] - ty) ** 2))
+    gpx = 2.0 * (fw["px"] - tx) / n
+    gpy = 2.0 * (fw["py"] - ty) / n
+    gvx = np.zeros(n)
+    gvy = np.zeros(n)
+    gprx = np.zeros(n)
+    gpry = np.zeros(n)
+    gtau = 0.0
+    for t in range(steps - 1, -1, -1):
+        st = dict(base, cls=cls)
+        st.update(fw["states"][t])
+        r = step_vjp(st, params, gpx, gpy, gvx, gvy, double_state=True)
+        gpx, gpy, gvx, gvy = r["g_px"], r["g_py"], r["g_vx"], r["g_vy"]
+        gprx += r["g_pref_x"]
+        gpry += r["g_pref_y"]
+        gtau += r["g_tau"]
+    return {"loss": loss, "g_pref_x": gprx, "g_pref_y": gpry, "g_tau": gtau,
+            "trace": fw["trace"], "final": fw}
 
 
 def step_batched(state, scene_off, scene_params, want_work: bool = False):

@@ -212,19 +212,22 @@ def c4_batched(seed: int = 4, n_scenes: int = 512, lo: int = 64, hi: int = 65536
                     scene_off=off, scene_params=plist, **cat)
 
 
-def c5_rollout(seed: int = 5, n: int = 16384, side: float = 240.0) -> Scenario:
+def c5_rollout(seed: int = 5, n: int = 16384, side: float = 240.0,
+               speed: float = 1.4) -> Scenario:
     """Differentiable rollout: 16,384 pedestrians uniform in 240 x 240 m,
-    v_pref = 1.5 m/s toward a uniform goal (held constant), targets of the
-    loss drawn from an independent stream; dt 0.1 s, tau 2 s, 5 m,
-    10 neighbours, 50 steps."""
+    v_pref = `speed` toward a uniform goal (held constant), targets of the
+    loss drawn from an independent stream; v_max 1.5 m/s, dt 0.1 s, tau 2 s,
+    5 m, 10 neighbours, 50 steps.  The desired speed sits below the cap: at
+    |v_pref| = v_max the speed-disc projection has a kink in v_pref, which
+    central differences would straddle."""
     rng = np.random.Generator(np.random.PCG64(seed))
     px = rng.uniform(0.0, side, size=n)
     py = rng.uniform(0.0, side, size=n)
     gx = rng.uniform(0.0, side, size=n)
     gy = rng.uniform(0.0, side, size=n)
     ang = np.arctan2(gy - py, gx - px)
-    vpx = 1.5 * np.cos(ang)
-    vpy = 1.5 * np.sin(ang)
+    vpx = speed * np.cos(ang)
+    vpy = speed * np.sin(ang)
     trng = np.random.Generator(np.random.PCG64(seed + 1000))
     tx = trng.uniform(0.0, side, size=n)
     ty = trng.uniform(0.0, side, size=n)

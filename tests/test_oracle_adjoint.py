@@ -1,0 +1,187 @@
+"""Pins of the oracle's gradient of the ORCA step (the differentiable form).
+
+The oracle differentiates its own forward code with forward-mode dual
+numbers at fixed branch decisions.  It is pinned here by
+  * closed-form derivatives of two-agent cases (head-on pedestrians in the
+    cutoff-arc case: v_A'.x = (v_A.x + v_B.x)/2 + (d - R)/(2 tau); a single
+    active line: d d^T; the speed disc: (v_max/|v_pref|)(I - u u^T));
+  * FP64 central finite differences of one step and of whole rollouts, with
+    the trace hash of branch outcomes used to discard perturbations that cross
+    a kink (a different neighbour set, LP regime, active line or VO branch).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2008_11578_amd import scenarios
+
+F32 = np.float32
+
+
+def _params(**kw):
+    p = dict(dt=0.1, time_horizon=2.0, neighbor_dist=6.0, max_neighbors=10, pref_is_goal=0,
+             f=((0.5, 1.0), (0.0, 0.5)), par_eps=1e-5, cell_size=0.0)
+    p.update(kw)
+    return p
+
+
+def _pair(d, s):
+    return dict(px=np.array([0.0, d]), py=np.zeros(2), vx=np.array([s, -s]), vy=np.zeros(2),
+                pref_x=np.array([s, -s]), pref_y=np.zeros(2), radius=np.full(2, 0.3),
+                max_speed=np.full(2, 1.5), cls=np.zeros(2, np.uint8))
+
+
+def _vjp(oracle_mod, st, prm, gvx=None, gvy=None, gpx=None, gpy=None):
+    n = len(st["px"])
+    z = np.zeros(n)
+    return oracle_mod.step_vjp(st, prm, z if gpx is None else gpx, z if gpy is None else gpy,
+                               z if gvx is None else gvx, z if gvy is None else gvy,
+                               double_state=True)
+
+
+def test_closed_form_tau_derivative_head_on(oracle_mod):
+    d, s, tau = 4.3, 1.0, 2.0
+    st = _pair(d, s)
+    prm = _params(time_horizon=tau)
+    R = 0.6
+    r = _vjp(oracle_mod, st, prm, gvx=np.array([1.0, 0.0]))
+    # v_A' = (d - R) / (2 tau)  =>  dv_A'/dtau = -(d - R) / (2 tau^2)
+    np.testing.assert_allclose(r["g_tau"], -(d - R) / (2 * tau * tau), rtol=1e-12)
+    # the active line is x <= c: v_A'.y follows v_pref.y, v_A'.x does not
+    r = _vjp(oracle_mod, st, prm, gvy=np.array([1.0, 0.0]))
+    np.testing.assert_allclose([r["g_pref_x"][0], r["g_pref_y"][0]], [0.0, 1.0], atol=1e-14)
+    # dv_A'.x/dp_B.x = 1/(2 tau) and dv_A'.x/dp_A.x = -1/(2 tau) (plus 0 direct)
+    r = _vjp(oracle_mod, st, prm, gvx=np.array([1.0, 0.0]))
+    np.testing.assert_allclose([r["g_px"][0], r["g_px"][1]], [-1 / (2 * tau), 1 / (2 * tau)],
+                               rtol=1e-12)
+    # in the arc case q_A.x = (v_A.x + v_B.x)/2 + (d - R)/(2 tau): each velocity
+    # enters with weight 1/2
+    np.testing.assert_allclose([r["g_vx"][0], r["g_vx"][1]], [0.5, 0.5], rtol=1e-12)
+
+
+def test_closed_form_disc_and_free(oracle_mod):
+    # a lone agent: v' = v_pref inside the disc, v_max * u outside
+    st = dict(px=np.zeros(1), py=np.zeros(1), vx=np.zeros(1), vy=np.zeros(1),
+              pref_x=np.array([3.0]), pref_y=np.array([4.0]), radius=np.full(1, 0.3),
+              max_speed=np.full(1, 1.5), cls=np.zeros(1, np.uint8))
+    u = np.array([0.6, 0.8])
+    J = 1.5 / 5.0 * (np.eye(2) - np.outer(u, u))
+    for c in (np.array([1.0, 0.0]), np.array([0.0, 1.0])):
+        r = _vjp(oracle_mod, st, _params(), gvx=c[:1], gvy=c[1:])
+        np.testing.assert_allclose([r["g_pref_x"][0], r["g_pref_y"][0]], J.T @ c, atol=1e-14)
+    st["pref_x"] = np.array([0.3])
+    st["pref_y"] = np.array([-0.4])
+    r = _vjp(oracle_mod, st, _params(), gvx=np.array([1.0]), gvy=np.array([2.0]))
+    np.testing.assert_allclose([r["g_pref_x"][0], r["g_pref_y"][0]], [1.0, 2.0], atol=1e-15)
+    # p' = p + v' dt: the direct position term passes through unchanged
+    r = _vjp(oracle_mod, st, _params(), gpx=np.array([1.0]))
+    np.testing.assert_allclose([r["g_px"][0], r["g_pref_x"][0]], [1.0, float(F32(0.1))], rtol=1e-12)
+
+
+def _crowd(seed, n=160, side=14.0, goal=False):
+    sc = scenarios.random_state(n, side, seed=seed, n_vehicles=n // 10,
+                                params=scenarios.Params(dt=0.1, neighbor_dist=5.0,
+                                                        max_neighbors=10,
+                                                        pref_is_goal=int(goal)))
+    st = {k: np.asarray(getattr(sc, k), np.float64) for k in
+          ("px", "py", "vx", "vy", "pref_x", "pref_y", "radius", "max_speed")}
+    st["cls"] = sc.cls
+    if not goal:
+        rng = np.random.default_rng(seed + 1)
+        ang = rng.uniform(0, 2 * math.pi, n)
+        st["pref_x"] = 1.4 * np.cos(ang)
+        st["pref_y"] = 1.4 * np.sin(ang)
+    return st, sc.params
+
+
+def _step_loss(oracle_mod, st, prm, cot):
+    o = oracle_mod.rollout(st, prm, 1)
+    val = sum(float(np.dot(cot[k], o[k])) for k in ("px", "py", "vx", "vy"))
+    return val, o["trace"]
+
+
+@pytest.mark.parametrize("goal", [False, True])
+def test_one_step_vjp_matches_central_differences(oracle_mod, goal):
+    st, prm = _crowd(3 + goal, goal=goal)
+    n = len(st["px"])
+    rng = np.random.default_rng(11)
+    cot = {k: rng.normal(size=n) for k in ("px", "py", "vx", "vy")}
+    g = oracle_mod.step_vjp(st, prm, cot["px"], cot["py"], cot["vx"], cot["vy"],
+                            double_state=True)
+    base, tr0 = _step_loss(oracle_mod, st, prm, cot)
+    h = 1e-6
+    checked = skipped = 0
+    fields = [("px", "g_px"), ("py", "g_py"), ("vx", "g_vx"), ("vy", "g_vy"),
+              ("pref_x", "g_pref_x"), ("pref_y", "g_pref_y")]
+    trial = 0
+    while checked < 40 and trial < 120:
+        f, gk = fields[trial % len(fields)]
+        trial += 1
+        i = int(rng.integers(0, n))
+        sp = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in st.items()}
+        sm = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in st.items()}
+        sp[f][i] += h
+        sm[f][i] -= h
+        lp, trp = _step_loss(oracle_mod, sp, prm, cot)
+        lm, trm = _step_loss(oracle_mod, sm, prm, cot)
+        if trp != tr0 or trm != tr0:
+            skipped += 1
+            continue
+        fd = (lp - lm) / (2 * h)
+        an = g[gk][i]
+        assert abs(an - fd) <= 1e-5 * max(1.0, abs(fd)), (f, i, an, fd)
+        checked += 1
+    # tau
+    pp = dict(prm.as_dict())
+    pm = dict(prm.as_dict())
+    tau = float(np.float32(prm.time_horizon))
+    pp["time_horizon"] = tau + 1e-4
+    pm["time_horizon"] = tau - 1e-4
+    lp, trp = _step_loss(oracle_mod, st, pp, cot)
+    lm, trm = _step_loss(oracle_mod, st, pm, cot)
+    if trp == tr0 and trm == tr0:
+        # scalar parameters reach the oracle rounded to FP32
+        fd = (lp - lm) / (float(F32(tau + 1e-4)) - float(F32(tau - 1e-4)))
+        assert abs(g["g_tau"] - fd) <= 1e-4 * max(1.0, abs(fd)), (g["g_tau"], fd)
+    # goal mode puts |v_pref| exactly on the speed cap far from the goal, a
+    # genuine kink of the derivative that perturbations keep crossing
+    assert checked >= 40 and skipped <= 60
+
+
+def test_rollout_gradient_matches_central_differences(oracle_mod):
+    sc = scenarios.c5_rollout(n=400, side=38.0)
+    prm = sc.params
+    steps = 12
+    st = {k: getattr(sc, k) for k in ("px", "py", "vx", "vy", "pref_x", "pref_y", "radius",
+                                       "max_speed", "cls")}
+    res = oracle_mod.rollout_grad(st, prm, steps, sc.target_x, sc.target_y)
+
+    def loss(stx, p):
+        o = oracle_mod.rollout(stx, p, steps)
+        return float(np.mean((o["px"] - sc.target_x) ** 2 + (o["py"] - sc.target_y) ** 2)), o["trace"]
+
+    base, tr0 = loss(st, prm)
+    np.testing.assert_allclose(base, res["loss"], rtol=1e-14)
+    rng = np.random.default_rng(5)
+    h = 1e-6
+    checked = resampled = 0
+    while checked < 12 and resampled < 30:
+        which = int(rng.integers(0, 2))
+        i = int(rng.integers(0, sc.n))
+        f = ("pref_x", "pref_y")[which]
+        sp = {k: np.array(v, dtype=np.float64 if k != "cls" else np.uint8) for k, v in st.items()}
+        sm = {k: np.array(v, dtype=np.float64 if k != "cls" else np.uint8) for k, v in st.items()}
+        sp[f][i] += h
+        sm[f][i] -= h
+        lp, trp = loss(sp, prm)
+        lm, trm = loss(sm, prm)
+        if trp != tr0 or trm != tr0:
+            resampled += 1
+            continue
+        fd = (lp - lm) / (2 * h)
+        an = res["g_" + f][i]
+        scale = max(abs(fd), 1e-3 * np.max(np.abs(res["g_pref_x"])))
+        assert abs(an - fd) <= 1e-4 * scale, (f, i, an, fd)
+        checked += 1
+    assert checked >= 10

@@ -56,5 +56,6 @@ def test_c5_rollout_targets():
     sc = scenarios.c5_rollout(n=512)
     assert sc.params.pref_is_goal == 0
     sp = np.hypot(sc.pref_x, sc.pref_y)
-    np.testing.assert_allclose(sp, 1.5, rtol=1e-6)
+    np.testing.assert_allclose(sp, 1.4, rtol=1e-6)
+    assert (sp < sc.max_speed).all()
     assert sc.target_x is not None and sc.target_x.shape == (512,)
