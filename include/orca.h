@@ -155,6 +155,40 @@ typedef struct {
 int orca_step_batched(const orca_agents_in *in, const orca_agents_out *out, int32_t n,
                       const orca_batch *batch, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Cotangents (gradients of a scalar loss) of an agent state, device
+ * pointers, length n, caller order. */
+typedef struct {
+    const float *px, *py, *vx, *vy;
+} orca_cotangents;
+
+/* Outputs of orca_step_backward: px..vy are overwritten with the cotangents
+ * of the step-t state (they may alias the inputs of orca_cotangents);
+ * pref_x / pref_y (cotangents of the pref input: the desired velocity, or
+ * the goal in goal mode) are ACCUMULATED (+=); tau (nullable, one device
+ * float) is accumulated with the cotangent of the shared look-ahead time. */
+typedef struct {
+    float *px, *py, *vx, *vy;
+    float *pref_x, *pref_y;
+    float *tau;
+} orca_cotangents_out;
+
+/* Workspace bytes of orca_step_backward for n agents (max_cells as for
+ * orca_workspace_bytes). */
+size_t orca_backward_workspace_bytes(int32_t n, int32_t max_cells);
+
+/* Adjoint (vector-Jacobian product) of orca_step at state `in` (the
+ * differentiable form; not in the paper).  Given the cotangents g1 of the
+ * step's outputs (p' = p + v' dt, v'), writes the cotangents of p and v and
+ * accumulates those of the pref input and tau.  The step is recomputed
+ * exactly (same neighbours, half-planes and LP); neighbour sets and all
+ * branch decisions are held fixed, and the LP result is differentiated
+ * through its active constraints (implicit differentiation).  Contributions
+ * to neighbours are gathered in a fixed order, so results are
+ * bit-reproducible.  Radii, speed caps, f and dt are constants. */
+int orca_step_backward(const orca_agents_in *in, int32_t n, const orca_params *params,
+                       const orca_cotangents *g1, const orca_cotangents_out *g0, void *ws,
+                       size_t ws_bytes, hipStream_t stream);
+
 /* Human-readable text for a status code (static storage). */
 const char *orca_status_string(int code);
 

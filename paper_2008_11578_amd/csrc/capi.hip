@@ -65,6 +65,36 @@ Work bind(const Layout &L, void *ws)
     return w;
 }
 
+size_t adjoint_extra_bytes(int64_t n)
+{
+    const size_t a = align_up(sizeof(float) * (size_t)n) + align_up(sizeof(int32_t) * 3 * (size_t)n) +
+                     align_up(sizeof(float4) * 3 * (size_t)n) +
+                     2 * align_up(sizeof(uint32_t) * 3 * (size_t)n) +
+                     2 * align_up(sizeof(uint32_t) * (size_t)n);
+    return a;
+}
+
+AdjointBufs bind_adjoint(int64_t n, void *base)
+{
+    char *b = (char *)base;
+    AdjointBufs r;
+    size_t o = 0;
+    r.tau_part = (float *)(b + o);
+    o += align_up(sizeof(float) * (size_t)n);
+    r.e_tgt = (int32_t *)(b + o);
+    o += align_up(sizeof(int32_t) * 3 * (size_t)n);
+    r.e_val = (float4 *)(b + o);
+    o += align_up(sizeof(float4) * 3 * (size_t)n);
+    r.e_rank = (uint32_t *)(b + o);
+    o += align_up(sizeof(uint32_t) * 3 * (size_t)n);
+    r.e_list = (uint32_t *)(b + o);
+    o += align_up(sizeof(uint32_t) * 3 * (size_t)n);
+    r.e_cnt = (uint32_t *)(b + o);
+    o += align_up(sizeof(uint32_t) * (size_t)n);
+    r.e_start = (uint32_t *)(b + o);
+    return r;
+}
+
 namespace {
 
 // The workspace size fixes max_cells for a given n: the largest cell count
@@ -221,6 +251,42 @@ int orca_step_batched(const orca_agents_in *in, const orca_agents_out *out, int3
     if (launch_batched(*in, *out, n, batch->scene_off, batch->n_scenes, batch->params,
                        batch->max_neighbors, L, w, batch->error_flag, batch->mode,
                        stream) != hipSuccess)
+        return ORCA_EHIP;
+    return ORCA_OK;
+}
+
+size_t orca_backward_workspace_bytes(int32_t n, int32_t max_cells)
+{
+    if (n < 0 || max_cells < 0) return 0;
+    return make_layout(n, 0, max_cells).total + adjoint_extra_bytes(n);
+}
+
+int orca_step_backward(const orca_agents_in *in, int32_t n, const orca_params *params,
+                       const orca_cotangents *g1, const orca_cotangents_out *g0, void *ws,
+                       size_t ws_bytes, hipStream_t stream)
+{
+    if (n < 0) return ORCA_EINVAL;
+    int rc = check_params(params);
+    if (rc != ORCA_OK) return rc;
+    if (n == 0) return ORCA_OK;
+    rc = check_in(in);
+    if (rc != ORCA_OK) return rc;
+    if (!g1 || !g1->px || !g1->py || !g1->vx || !g1->vy) return ORCA_EINVAL;
+    if (!g0 || !g0->px || !g0->py || !g0->vx || !g0->vy || !g0->pref_x || !g0->pref_y)
+        return ORCA_EINVAL;
+    if (!ws) return ORCA_EINVAL;
+    const size_t extra = adjoint_extra_bytes(n);
+    if (ws_bytes <= extra) return ORCA_EWORKSPACE;
+    int64_t mc = max_cells_for(n, 0, ws_bytes - extra);
+    if (mc <= 0) return ORCA_EWORKSPACE;
+    if (mc > kMaxCellsCap) mc = kMaxCellsCap;
+    const Layout L = make_layout(n, 0, mc);
+    if (L.total + extra > ws_bytes) return ORCA_EWORKSPACE;
+    const Work w = bind(L, ws);
+    const AdjointBufs b = bind_adjoint(n, (char *)ws + L.total);
+    if (launch_grid_build(*in, n, *params, L, w, stream) != hipSuccess) return ORCA_EHIP;
+    if (launch_adjoint(*in, n, *params, L, w, b, g1->px, g1->py, g1->vx, g1->vy, g0->px, g0->py,
+                       g0->vx, g0->vy, g0->pref_x, g0->pref_y, g0->tau, stream) != hipSuccess)
         return ORCA_EHIP;
     return ORCA_OK;
 }

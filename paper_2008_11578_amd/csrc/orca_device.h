@@ -359,20 +359,41 @@ struct ProjLines {
     }
 };
 
+// The constraints that define an LP result (its active set), recorded by
+// the adjoint's recomputation of the step.  LP2 results: kFree (v = v_pref),
+// kDisc (v_pref scaled onto the speed circle), kLine (projection of v_pref
+// onto line a), kLineLine (intersection of lines a and b), kLineDisc (line a
+// on the speed circle).  LP3 results, for the line i3 whose penetration was
+// minimised last: kDir (v_max times i3's inward normal), kProjDisc (the
+// equal-penetration boundary of a and i3 on the circle), kProjProj (the
+// point of equal penetration of a, b and i3), kTie (v_pref projected onto
+// the boundary of a and i3).
+enum ActiveKind { kFree = 0, kDisc, kLine, kLineLine, kLineDisc, kDir, kProjDisc, kProjProj, kTie };
+
+struct ActiveSet {
+    int kind;
+    int i3;
+    int a, b;
+};
+
 // One-dimensional sub-problem on line li (index i): the parameter interval
 // inside the speed disc and on the permitted side of every valid line j < i.
 // mode 0: closest point to (ox, oy); mode 1: extreme along unit (ox, oy), or,
 // when the line is orthogonal to it, the point closest to (tx, ty).
+// `how` reports what fixed the result: 0 projection, 1 / 2 the lower / upper
+// end of the interval (bounded by line `src`, or by the disc when src < 0),
+// 3 the tie projection.
 template <class Src>
 __device__ __forceinline__ bool lp1(const Src &src, int i, float4 li, float vmax, int mode,
                                     float ox, float oy, float tx, float ty, float eps, float &x,
-                                    float &y)
+                                    float &y, int &how, int &bound)
 {
     const float dot = li.x * li.z + li.y * li.w;
     const float disc = dot * dot + vmax * vmax - (li.x * li.x + li.y * li.y);
     if (disc < 0.0f) return false;
     const float sq = sqrtf(disc);
     float tl = -dot - sq, tr = -dot + sq;
+    int sl = -1, sr = -1;
     for (int j = 0; j < i; ++j) {
         float4 lj;
         if (!src.get(j, lj)) continue;
@@ -383,25 +404,42 @@ __device__ __forceinline__ bool lp1(const Src &src, int i, float4 li, float vmax
             continue;
         }
         const float t = -b / a;
-        if (a > 0.0f)
-            tl = fmaxf(tl, t);
-        else
-            tr = fminf(tr, t);
+        if (a > 0.0f) {
+            if (t > tl) {
+                tl = t;
+                sl = j;
+            }
+        } else {
+            if (t < tr) {
+                tr = t;
+                sr = j;
+            }
+        }
         if (tl > tr) return false;
     }
     float t;
     if (mode == 0) {
         t = li.z * (ox - li.x) + li.w * (oy - li.y);
-        t = fminf(fmaxf(t, tl), tr);
+        how = 0;
     } else {
         const float sd = ox * li.z + oy * li.w;
         if (fabsf(sd) <= eps) {
             t = li.z * (tx - li.x) + li.w * (ty - li.y);
-            t = fminf(fmaxf(t, tl), tr);
+            how = 3;
         } else {
             t = sd > 0.0f ? tr : tl;
+            how = sd > 0.0f ? 2 : 1;
         }
     }
+    if (t < tl) {
+        t = tl;
+        how = 1;
+    }
+    if (t > tr) {
+        t = tr;
+        how = 2;
+    }
+    bound = how == 1 ? sl : (how == 2 ? sr : -1);
     x = li.x + t * li.z;
     y = li.y + t * li.w;
     return true;
@@ -409,23 +447,28 @@ __device__ __forceinline__ bool lp1(const Src &src, int i, float4 li, float vmax
 
 // Incremental 2D LP over lines 0..m-1 of `src` and the disc |v| <= vmax.
 // Returns the first infeasible line, or m; v keeps its pre-failure value.
-template <class Src>
+// With REC the active set of the result is written to *rec.
+template <bool REC, class Src>
 __device__ __forceinline__ int lp2(const Src &src, int m, float vmax, int mode, float ox,
-                                   float oy, float tx, float ty, float eps, float &vx, float &vy)
+                                   float oy, float tx, float ty, float eps, float &vx, float &vy,
+                                   ActiveSet *rec)
 {
     float x, y;
     if (mode == 1) {
         x = ox * vmax;
         y = oy * vmax;
+        if (REC) rec->kind = kDir;
     } else {
         const float o2 = ox * ox + oy * oy;
         if (o2 > vmax * vmax) {
             const float sc = vmax / sqrtf(o2);
             x = ox * sc;
             y = oy * sc;
+            if (REC) rec->kind = kDisc;
         } else {
             x = ox;
             y = oy;
+            if (REC) rec->kind = kFree;
         }
     }
     for (int i = 0; i < m; ++i) {
@@ -433,13 +476,22 @@ __device__ __forceinline__ int lp2(const Src &src, int m, float vmax, int mode, 
         if (!src.get(i, li)) continue;
         if (det2(li.z, li.w, li.x - x, li.y - y) > 0.0f) {
             float nx = x, ny = y;
-            if (!lp1(src, i, li, vmax, mode, ox, oy, tx, ty, eps, nx, ny)) {
+            int how, bound;
+            if (!lp1(src, i, li, vmax, mode, ox, oy, tx, ty, eps, nx, ny, how, bound)) {
                 vx = x;
                 vy = y;
                 return i;
             }
             x = nx;
             y = ny;
+            if (REC) {
+                rec->a = i;
+                rec->b = bound;
+                if (mode == 0)
+                    rec->kind = how == 0 ? kLine : (bound >= 0 ? kLineLine : kLineDisc);
+                else
+                    rec->kind = how == 3 ? kTie : (bound >= 0 ? kProjProj : kProjDisc);
+            }
         }
     }
     vx = x;
@@ -451,9 +503,10 @@ __device__ __forceinline__ int lp2(const Src &src, int m, float vmax, int mode, 
 // later line i whose penetration exceeds the current level re-solves v in the
 // region where no earlier line penetrates more than line i, as deep into line
 // i's permitted side as possible.
-template <int BLOCK>
+template <bool REC, int BLOCK>
 __device__ __forceinline__ void lp3(const float4 *L, int tid, int m, int fail, float vmax,
-                                    float tx, float ty, float eps, float &vx, float &vy)
+                                    float tx, float ty, float eps, float &vx, float &vy,
+                                    ActiveSet *rec)
 {
     float level = 0.0f;
     float x = vx, y = vy;
@@ -462,9 +515,14 @@ __device__ __forceinline__ void lp3(const float4 *L, int tid, int m, int fail, f
         if (det2(li.z, li.w, li.x - x, li.y - y) <= level) continue;
         ProjLines<BLOCK> src{L, tid, li, det2(li.z, li.w, li.x, li.y), eps};
         float nx = x, ny = y;
-        if (lp2(src, i, vmax, 1, -li.w, li.z, tx, ty, eps, nx, ny) == i) {
+        ActiveSet inner;
+        if (lp2<REC>(src, i, vmax, 1, -li.w, li.z, tx, ty, eps, nx, ny, &inner) == i) {
             x = nx;
             y = ny;
+            if (REC) {
+                *rec = inner;
+                rec->i3 = i;
+            }
         }
         level = det2(li.z, li.w, li.x - x, li.y - y);
     }
@@ -546,10 +604,10 @@ __device__ __forceinline__ void step_agent(int s, const GridMeta &g, const Scene
 
     LdsLines<BLOCK> src{lines, tid};
     float vx, vy;
-    const int fail = lp2(src, m, vmax, 0, prx, pry, 0.0f, 0.0f, p.eps, vx, vy);
+    const int fail = lp2<false>(src, m, vmax, 0, prx, pry, 0.0f, 0.0f, p.eps, vx, vy, nullptr);
     uint8_t st = 0;
     if (fail < m) {
-        lp3<BLOCK>(lines, tid, m, fail, vmax, prx, pry, p.eps, vx, vy);
+        lp3<false, BLOCK>(lines, tid, m, fail, vmax, prx, pry, p.eps, vx, vy, nullptr);
         st = 1;
     }
     out.vx[i] = vx;

@@ -194,4 +194,25 @@ hipError_t launch_knn_export(const orca_agents_in &in, int n, const orca_params 
 
 hipError_t launch_fill_zero(void *ws, size_t bytes, hipStream_t stream);
 
+// Extra workspace of the adjoint: per-agent tau contributions and the edge
+// list (3 per agent) of contributions to neighbours with its transpose.
+struct AdjointBufs {
+    float *tau_part;     // n
+    int32_t *e_tgt;      // 3n: target agent or -1
+    float4 *e_val;       // 3n: (gp.x, gp.y, gv.x, gv.y) for the target
+    uint32_t *e_rank;    // 3n
+    uint32_t *e_list;    // 3n
+    uint32_t *e_cnt;     // n
+    uint32_t *e_start;   // n
+};
+
+size_t adjoint_extra_bytes(int64_t n);
+AdjointBufs bind_adjoint(int64_t n, void *base);
+
+hipError_t launch_adjoint(const orca_agents_in &in, int n, const orca_params &prm,
+                          const Layout &L, const Work &w, const AdjointBufs &b,
+                          const float *gpx1, const float *gpy1, const float *gvx1,
+                          const float *gvy1, float *gpx0, float *gpy0, float *gvx0, float *gvy0,
+                          float *gprx, float *gpry, float *g_tau, hipStream_t stream);
+
 }  // namespace orca

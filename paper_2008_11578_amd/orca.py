@@ -51,6 +51,14 @@ class OrcaBatch(ctypes.Structure):
                 ("mode", ctypes.c_int32), ("error_flag", ctypes.c_void_p)]
 
 
+class Cotangents(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("px", "py", "vx", "vy")]
+
+
+class CotangentsOut(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("px", "py", "vx", "vy", "pref_x", "pref_y", "tau")]
+
+
 class StepEvents(ctypes.Structure):
     _fields_ = [("grid_begin", ctypes.c_void_p), ("step_begin", ctypes.c_void_p),
                 ("step_end", ctypes.c_void_p)]
@@ -86,6 +94,12 @@ def lib() -> ctypes.CDLL:
         L.orca_step_batched.restype = ctypes.c_int
         L.orca_step_batched.argtypes = [ctypes.POINTER(AgentsIn), ctypes.POINTER(AgentsOut), i32,
                                         ctypes.POINTER(OrcaBatch), vp, sz, vp]
+        L.orca_backward_workspace_bytes.restype = sz
+        L.orca_backward_workspace_bytes.argtypes = [i32, i32]
+        L.orca_step_backward.restype = ctypes.c_int
+        L.orca_step_backward.argtypes = [ctypes.POINTER(AgentsIn), i32, ctypes.POINTER(OrcaParams),
+                                         ctypes.POINTER(Cotangents), ctypes.POINTER(CotangentsOut),
+                                         vp, sz, vp]
         L.orca_status_string.restype = ctypes.c_char_p
         L.orca_status_string.argtypes = [ctypes.c_int]
         L.orca_version.restype = ctypes.c_char_p
@@ -181,10 +195,15 @@ def workspace_bytes(n: int, n_scenes: int = 0, max_cells: int = 0) -> int:
 
 
 class Workspace:
-    """A caller-owned device workspace, zero-filled once on creation."""
+    """A caller-owned device workspace, zero-filled once on creation.  With
+    backward=True it is sized for orca_step_backward."""
 
-    def __init__(self, n: int, n_scenes: int = 0, max_cells: int = 0, device="cuda"):
-        self.nbytes = workspace_bytes(n, n_scenes, max_cells)
+    def __init__(self, n: int, n_scenes: int = 0, max_cells: int = 0, device="cuda",
+                 backward: bool = False):
+        if backward:
+            self.nbytes = int(lib().orca_backward_workspace_bytes(int(n), int(max_cells)))
+        else:
+            self.nbytes = workspace_bytes(n, n_scenes, max_cells)
         self.buf = torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device=device)
         rc = lib().orca_workspace_init(_ptr(self.buf), self.nbytes, _stream_handle())
         if rc != ORCA_OK:
@@ -283,4 +302,34 @@ def step_batched(state: State, batch: Batch, ws: Workspace, out: Optional[State]
                                  ws.ptr(), ws.nbytes, _stream_handle(stream))
     if rc != ORCA_OK:
         raise OrcaError("orca_step_batched", rc)
+    return out
+
+
+def step_backward(state: State, params, ws: Workspace, g_px, g_py, g_vx, g_vy,
+                  g_pref_x: torch.Tensor, g_pref_y: torch.Tensor,
+                  g_tau: Optional[torch.Tensor] = None, out=None, stream=None):
+    """Adjoint of one step at `state` (``orca_step_backward``).  g_* are the
+    cotangents of the step's outputs; returns (g_px0, g_py0, g_vx0, g_vy0),
+    written into `out` (a 4-tuple of tensors, which may be the inputs) or new
+    tensors.  g_pref_x/g_pref_y and g_tau (one float) are accumulated."""
+    n = state.n
+    gin = (g_px, g_py, g_vx, g_vy)
+    for k, t in zip(("g_px", "g_py", "g_vx", "g_vy"), gin):
+        _check(t, k, torch.float32, n)
+    if out is None:
+        out = tuple(torch.empty_like(t) for t in gin)
+    for t in out:
+        _check(t, "out", torch.float32, n)
+    _check(g_pref_x, "g_pref_x", torch.float32, n)
+    _check(g_pref_y, "g_pref_y", torch.float32, n)
+    if g_tau is not None:
+        _check(g_tau, "g_tau", torch.float32, 1)
+    p = make_params(params)
+    ain = state.agents_in()
+    c1 = Cotangents(*[_ptr(t) for t in gin])
+    c0 = CotangentsOut(*[_ptr(t) for t in out], _ptr(g_pref_x), _ptr(g_pref_y), _ptr(g_tau))
+    rc = lib().orca_step_backward(ctypes.byref(ain), n, ctypes.byref(p), ctypes.byref(c1),
+                                  ctypes.byref(c0), ws.ptr(), ws.nbytes, _stream_handle(stream))
+    if rc != ORCA_OK:
+        raise OrcaError("orca_step_backward", rc)
     return out

@@ -1,0 +1,143 @@
+"""GPU adjoint (orca_step_backward and the checkpointed rollout) against the
+oracle's forward-mode gradient, from identical FP32 states.
+
+The oracle VJP is itself pinned to closed forms and FP64 finite differences
+(tests/test_oracle_adjoint.py); here the hand-written FP32 adjoint must agree
+with it one step at a time, and a whole checkpointed rollout gradient must
+agree with the oracle's VJPs chained backwards along the GPU's own
+trajectory (which separates the adjoint's maths from FP32 trajectory drift).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2008_11578_amd import scenarios
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def _advanced_state(n=4096, steps=8, seed=5):
+    import torch
+    from paper_2008_11578_amd import orca
+    sc = scenarios.c5_rollout(seed=seed, n=n, side=240.0 * np.sqrt(n / 16384))
+    st = orca.State.from_arrays(sc)
+    nxt = st.clone()
+    ws = orca.Workspace(st.n)
+    for _ in range(steps):
+        orca.step(st, sc.params, ws, out=nxt)
+        st, nxt = nxt, st
+    torch.cuda.synchronize()
+    return sc, st
+
+
+def _gpu_vjp(st, params, cot):
+    import torch
+    from paper_2008_11578_amd import orca
+    n = st.n
+    g = [torch.as_tensor(c).cuda() for c in cot]
+    gpr = torch.zeros(n, device="cuda")
+    gpy = torch.zeros(n, device="cuda")
+    gt = torch.zeros(1, device="cuda")
+    out = orca.step_backward(st, params, orca.Workspace(n, backward=True), *g, gpr, gpy, gt)
+    torch.cuda.synchronize()
+    return [t.cpu().numpy() for t in out], gpr.cpu().numpy(), gpy.cpu().numpy(), float(gt.item())
+
+
+@pytest.mark.parametrize("goal", [0, 1])
+def test_step_backward_matches_oracle(goal):
+    import dataclasses
+    sc, st = _advanced_state()
+    params = dataclasses.replace(sc.params, pref_is_goal=goal)
+    S = st.to_numpy()
+    if goal:
+        # goals far enough away that the desired speed is capped or arriving
+        rng = np.random.default_rng(9)
+        S["pref_x"] = (S["px"] + rng.uniform(-30, 30, st.n)).astype(np.float32)
+        S["pref_y"] = (S["py"] + rng.uniform(-30, 30, st.n)).astype(np.float32)
+        from paper_2008_11578_amd import orca
+        st = orca.State.from_arrays(S)
+    rng = np.random.default_rng(3)
+    cot = [rng.normal(size=st.n).astype(np.float32) for _ in range(4)]
+    (gpx, gpy, gvx, gvy), gprx, gpry, gtau = _gpu_vjp(st, params, cot)
+    o = oracle.step_vjp(S, params, *[c.astype(np.float64) for c in cot])
+    for a, k, tol in ((gvx, "g_vx", 1e-4), (gvy, "g_vy", 1e-4), (gprx, "g_pref_x", 1e-4),
+                      (gpry, "g_pref_y", 1e-4), (gpx, "g_px", 5e-3), (gpy, "g_py", 5e-3)):
+        assert rel(a, o[k]) <= tol, (k, rel(a, o[k]))
+        # no single agent off by more than 1e-3 of the largest cotangent; in
+        # goal mode v_pref depends on p with gain up to 1/dt and a derivative
+        # kink at the arrival radius |g - p| = v_max dt, where FP32 and FP64
+        # may take different sides, so the bound there is 1e-2
+        per = 1e-2 if goal and k in ("g_px", "g_py") else 1e-3
+        assert np.max(np.abs(a - o[k])) <= per * np.max(np.abs(o[k])), k
+    assert abs(gtau - o["g_tau"]) <= 1e-4 * abs(o["g_tau"])
+
+
+def test_step_backward_deterministic_and_inplace():
+    import torch
+    from paper_2008_11578_amd import orca
+    sc, st = _advanced_state(n=2048)
+    rng = np.random.default_rng(4)
+    cot = [rng.normal(size=st.n).astype(np.float32) for _ in range(4)]
+    a = _gpu_vjp(st, sc.params, cot)
+    b = _gpu_vjp(st, sc.params, cot)
+    for x, y in zip(a[0], b[0]):
+        assert np.array_equal(x, y)
+    assert a[3] == b[3]
+    # in place: outputs overwrite the incoming cotangents
+    g = [torch.as_tensor(c).cuda() for c in cot]
+    gpr = torch.zeros(st.n, device="cuda")
+    gpy = torch.zeros(st.n, device="cuda")
+    orca.step_backward(st, sc.params, orca.Workspace(st.n, backward=True), *g, gpr, gpy,
+                       None, out=tuple(g))
+    torch.cuda.synchronize()
+    for x, y in zip(a[0], g):
+        assert np.array_equal(x, y.cpu().numpy())
+    assert np.array_equal(a[1], gpr.cpu().numpy())
+
+
+def test_rollout_gradient_matches_oracle_chain():
+    import torch
+    from paper_2008_11578_amd import orca, rollout
+    n, steps = 4096, 20
+    sc = scenarios.c5_rollout(n=n, side=120.0)
+    p = sc.params
+    st0 = orca.State.from_arrays(sc)
+    vpx = st0.pref_x.clone().requires_grad_(True)
+    vpy = st0.pref_y.clone().requires_grad_(True)
+    tau = torch.tensor(float(p.time_horizon), device="cuda", requires_grad=True)
+    tx = torch.as_tensor(sc.target_x).cuda()
+    ty = torch.as_tensor(sc.target_y).cuda()
+    px, py = rollout.rollout(vpx, vpy, tau, st0, p, steps=steps, ckpt=6)
+    loss = rollout.trajectory_loss(px, py, tx, ty)
+    loss.backward()
+    torch.cuda.synchronize()
+    # the GPU's own trajectory, then the oracle's VJPs chained backwards along it
+    ws = orca.Workspace(n)
+    s, s2 = st0.clone(), st0.clone()
+    states = []
+    for _ in range(steps):
+        states.append(s.to_numpy())
+        orca.step(s, p, ws, out=s2)
+        s, s2 = s2, s
+    fin = s.to_numpy()
+    np.testing.assert_array_equal(fin["px"], px.detach().cpu().numpy())
+    gpx = 2 * (fin["px"].astype(np.float64) - sc.target_x) / n
+    gpy = 2 * (fin["py"].astype(np.float64) - sc.target_y) / n
+    gvx = np.zeros(n)
+    gvy = np.zeros(n)
+    gprx = np.zeros(n)
+    gpry = np.zeros(n)
+    gtau = 0.0
+    for t in range(steps - 1, -1, -1):
+        r = oracle.step_vjp(states[t], p, gpx, gpy, gvx, gvy)
+        gpx, gpy, gvx, gvy = r["g_px"], r["g_py"], r["g_vx"], r["g_vy"]
+        gprx += r["g_pref_x"]
+        gpry += r["g_pref_y"]
+        gtau += r["g_tau"]
+    assert rel(vpx.grad.cpu().numpy(), gprx) <= 1e-3
+    assert rel(vpy.grad.cpu().numpy(), gpry) <= 1e-3
+    assert abs(tau.grad.item() - gtau) <= 1e-3 * abs(gtau)
