@@ -216,6 +216,47 @@ def bench_batched(steps: int):
                                              "mode": tuned["mode"]}}
 
 
+def bench_adjoint(reps: int = 3):
+    """Differentiable rollout: 16,384 agents, 50 steps, checkpoints every 10:
+    forward rollout, then the backward pass (segment replays and
+    orca_step_backward), timed with HIP events."""
+    import numpy as np
+    import torch
+    from paper_2008_11578_amd import orca, rollout, scenarios
+    sc = scenarios.c5_rollout()
+    p = sc.params
+    n, steps = sc.n, sc.steps
+    st0 = orca.State.from_arrays(sc)
+    tx = torch.as_tensor(sc.target_x).cuda()
+    ty = torch.as_tensor(sc.target_y).cuda()
+
+    def once():
+        vpx = st0.pref_x.clone().requires_grad_(True)
+        vpy = st0.pref_y.clone().requires_grad_(True)
+        tau = torch.tensor(float(np.float32(p.time_horizon)), device="cuda", requires_grad=True)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        px, py = rollout.rollout(vpx, vpy, tau, st0, p, steps=steps, ckpt=10)
+        loss = rollout.trajectory_loss(px, py, tx, ty)
+        e1.record()
+        loss.backward()
+        e2.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), e1.elapsed_time(e2), float(loss.item()), float(tau.grad.item())
+
+    once()
+    runs = [once() for _ in range(reps)]
+    fwd = float(np.median([r[0] for r in runs]))
+    bwd = float(np.median([r[1] for r in runs]))
+    log(f"[bench] adjoint {n} agents x {steps} steps: forward {fwd:.2f} ms, backward {bwd:.2f} ms")
+    return {"metric": "agent-steps/s of a differentiable rollout (forward + backward)",
+            "agents": n, "steps": steps, "checkpoint_every": 10, "forward_ms": fwd,
+            "backward_ms": bwd,
+            "agent_steps_per_s": n * steps / ((fwd + bwd) * 1e-3),
+            "backward_agent_steps_per_s": n * steps / (bwd * 1e-3),
+            "loss": runs[-1][2], "dL_dtau": runs[-1][3]}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,6 +271,8 @@ def main(argv=None):
                          "workload; 0 = library default R_n)")
     ap.add_argument("--batched-steps", type=int, default=100,
                     help="graph-captured steps of the 512-scene batched form (0 skips it)")
+    ap.add_argument("--no-adjoint", dest="adjoint", action="store_false",
+                    help="skip the differentiable-rollout leg")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) and exit: the "
                          "reference kernel for scaling HBM counters")
@@ -319,9 +362,10 @@ def main(argv=None):
                 "hbm_peak_GBs": HBM_PEAK_GBS, "source_hash": kh}
 
     batched = bench_batched(args.batched_steps) if args.batched_steps > 0 else None
+    adjoint = bench_adjoint() if args.adjoint else None
 
     out = {
-        "metric": "agent-steps/sec at 1M agents (ORCA+LP)",
+        "metric": "agent-steps/sec at 1M agents (ORCA+LP); batched & adjoint steps/sec",
         "value": value,
         "unit": "agent-steps/s",
         "n_gpus": 1,
@@ -341,6 +385,7 @@ def main(argv=None):
         "roofline": roof,
         "cpu_baseline": cpu,
         "batched": batched,
+        "adjoint": adjoint,
     }
     print(json.dumps(out), flush=True)
     return 0

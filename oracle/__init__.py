@@ -84,7 +84,12 @@ def _f32d(x) -> float:
 
 
 def make_params(params) -> _OParams:
-    """Accepts any object with the ``orca_params`` field names."""
+    """Accepts any object with the ``orca_params`` field names; scalars are
+    rounded to FP32, as the GPU library receives them.  An ``_OParams``
+    passes through unchanged (finite-difference pins perturb its FP64
+    fields directly)."""
+    if isinstance(params, _OParams):
+        return params
     g = params.get if isinstance(params, dict) else (lambda k: getattr(params, k))
     p = _OParams()
     p.dt = _f32d(g("dt"))
@@ -239,6 +244,26 @@ def step_vjp(state, params, g_px1, g_py1, g_vx1, g_vy1, double_state: bool = Fal
     return out
 
 
+def step_d(state, params):
+    """One step from an FP64 state (no rounding of the state to FP32).
+    Returns FP64 px, py, vx, vy and the per-agent trace hash of neighbour
+    lists and branch outcomes."""
+    g = state.get if isinstance(state, dict) else (lambda k: getattr(state, k))
+    cur = [np.ascontiguousarray(g(k), dtype=np.float64) for k in _STATE]
+    cls = np.ascontiguousarray(g("cls"), dtype=np.uint8)
+    n = cur[0].shape[0]
+    p = make_params(params)
+    out = {k: np.zeros(n) for k in ("px", "py", "vx", "vy")}
+    trace = np.zeros(n, np.uint64)
+    rc = lib().oracle_step_d(n, *[a.ctypes.data for a in cur], cls.ctypes.data, ctypes.byref(p),
+                             out["px"].ctypes.data, out["py"].ctypes.data, out["vx"].ctypes.data,
+                             out["vy"].ctypes.data, None, trace.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"oracle_step_d failed ({rc})")
+    out["trace"] = trace
+    return out
+
+
 def rollout(state, params, steps: int, keep_states: bool = False):
     """FP64 rollout: `steps` oracle steps carrying the state in double.
     Returns dict px, py, vx, vy (final), trace (hash of every agent's
@@ -246,26 +271,19 @@ def rollout(state, params, steps: int, keep_states: bool = False):
     keep_states, the list of per-step double states (step 0 first)."""
     g = state.get if isinstance(state, dict) else (lambda k: getattr(state, k))
     cur = {k: np.ascontiguousarray(g(k), dtype=np.float64) for k in _STATE}
-    cls = np.ascontiguousarray(g("cls"), dtype=np.uint8)
+    cur["cls"] = np.ascontiguousarray(g("cls"), dtype=np.uint8)
     n = cur["px"].shape[0]
     p = make_params(params)
     hist = []
     h = np.uint64(1469598103934665603)
-    trace = np.zeros(n, np.uint64)
     for _ in range(steps):
         if keep_states:
             hist.append({k: cur[k].copy() for k in ("px", "py", "vx", "vy")})
-        nxt = {k: np.zeros(n) for k in ("px", "py", "vx", "vy")}
-        rc = lib().oracle_step_d(n, *[cur[k].ctypes.data for k in _STATE], cls.ctypes.data,
-                                 ctypes.byref(p), nxt["px"].ctypes.data, nxt["py"].ctypes.data,
-                                 nxt["vx"].ctypes.data, nxt["vy"].ctypes.data, None,
-                                 trace.ctypes.data)
-        if rc != 0:
-            raise ValueError(f"oracle_step_d failed ({rc})")
+        nxt = step_d(cur, p)
         with np.errstate(over="ignore"):
             h = np.uint64((int(h) * 1099511628211 + int(np.bitwise_xor.reduce(
-                trace * np.arange(1, n + 1, dtype=np.uint64)))) % (1 << 64))
-        cur.update(nxt)
+                nxt["trace"] * np.arange(1, n + 1, dtype=np.uint64)))) % (1 << 64))
+        cur.update({k: nxt[k] for k in ("px", "py", "vx", "vy")})
     out = {k: cur[k] for k in ("px", "py", "vx", "vy")}
     out["trace"] = int(h)
     if keep_states:

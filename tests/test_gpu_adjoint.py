@@ -141,3 +141,50 @@ def test_rollout_gradient_matches_oracle_chain():
     assert rel(vpx.grad.cpu().numpy(), gprx) <= 1e-3
     assert rel(vpy.grad.cpu().numpy(), gpry) <= 1e-3
     assert abs(tau.grad.item() - gtau) <= 1e-3 * abs(gtau)
+
+
+def test_rollout_gradient_full_shape_matches_oracle_chain():
+    """16,384 agents, 50 steps, checkpoints every 10: the GPU gradient with
+    respect to all 32,768 desired-velocity components and tau against the
+    oracle's VJPs chained along the same (GPU) trajectory."""
+    import torch
+    from paper_2008_11578_amd import orca, rollout
+    sc = scenarios.c5_rollout()
+    p = sc.params
+    n, steps = sc.n, sc.steps
+    st0 = orca.State.from_arrays(sc)
+    vpx = st0.pref_x.clone().requires_grad_(True)
+    vpy = st0.pref_y.clone().requires_grad_(True)
+    tau = torch.tensor(float(np.float32(p.time_horizon)), device="cuda", requires_grad=True)
+    tx = torch.as_tensor(sc.target_x).cuda()
+    ty = torch.as_tensor(sc.target_y).cuda()
+    px, py = rollout.rollout(vpx, vpy, tau, st0, p, steps=steps, ckpt=10)
+    rollout.trajectory_loss(px, py, tx, ty).backward()
+    torch.cuda.synchronize()
+    ws = orca.Workspace(n)
+    s, s2 = st0.clone(), st0.clone()
+    states = []
+    for _ in range(steps):
+        states.append(s.to_numpy())
+        orca.step(s, p, ws, out=s2)
+        s, s2 = s2, s
+    fin = s.to_numpy()
+    gpx = 2 * (fin["px"].astype(np.float64) - sc.target_x) / n
+    gpy = 2 * (fin["py"].astype(np.float64) - sc.target_y) / n
+    gvx = np.zeros(n)
+    gvy = np.zeros(n)
+    gprx = np.zeros(n)
+    gpry = np.zeros(n)
+    gtau = 0.0
+    for t in range(steps - 1, -1, -1):
+        r = oracle.step_vjp(states[t], p, gpx, gpy, gvx, gvy)
+        gpx, gpy, gvx, gvy = r["g_px"], r["g_py"], r["g_vx"], r["g_vy"]
+        gprx += r["g_pref_x"]
+        gpry += r["g_pref_y"]
+        gtau += r["g_tau"]
+    gx = vpx.grad.cpu().numpy()
+    gy = vpy.grad.cpu().numpy()
+    print("full-shape rollout gradient rel err:", rel(gx, gprx), rel(gy, gpry), tau.grad.item(),
+          gtau, flush=True)
+    assert rel(gx, gprx) <= 1e-3 and rel(gy, gpry) <= 1e-3
+    assert abs(tau.grad.item() - gtau) <= 1e-3 * abs(gtau)

@@ -185,3 +185,106 @@ def test_rollout_gradient_matches_central_differences(oracle_mod):
         assert abs(an - fd) <= 1e-4 * scale, (f, i, an, fd)
         checked += 1
     assert checked >= 10
+
+
+def test_full_shape_rollout_gradient_matches_central_differences(oracle_mod):
+    """The differentiable workload at its real shape: 16,384 pedestrians,
+    50 steps.  The chained oracle gradient against FP64 central differences
+    of whole rollouts on 31 seeded desired-velocity components (h = 1e-6)
+    and on tau.  A perturbation whose rollout changes any neighbour set,
+    branch or active set (trace hash) is resampled and counted.  Error
+    measure: |g - fd| / max(|fd|, 1e-3 max|fd| over the sample) <= 1e-3.
+
+    tau needs more care: it moves every agent at every step, and at this size
+    the rollout meets a jump (an LP regime flip, a discontinuity of the
+    incremental least-penetration solution) about every 1e-8 of tau, and
+    bends sharply between jumps (nearly parallel active lines), so central
+    differences at h = 1e-9 and 2e-9 already disagree by a few 1e-3.  The
+    whole-rollout tau difference is therefore held to 1e-2 only; the tau
+    derivative of each of the 50 steps along the same trajectory is pinned
+    to 1e-3, and the chain that sums them is the one the desired-velocity
+    components pin."""
+    sc = scenarios.c5_rollout()
+    prm = sc.params
+    steps = sc.steps
+    n = sc.n
+    st = {k: np.array(getattr(sc, k), dtype=np.uint8 if k == "cls" else np.float64)
+          for k in ("px", "py", "vx", "vy", "pref_x", "pref_y", "radius", "max_speed", "cls")}
+    res = oracle_mod.rollout_grad(st, prm, steps, sc.target_x, sc.target_y)
+
+    def final(stx, p):
+        return oracle_mod.rollout(stx, p, steps)
+
+    def dloss(a, b, width):
+        # L(a) - L(b) written as mean((a - b)(a + b - 2 target)), which keeps
+        # the difference free of the cancellation in L itself (L ~ 2e4)
+        d = ((a["px"] - b["px"]) * (a["px"] + b["px"] - 2 * sc.target_x)
+             + (a["py"] - b["py"]) * (a["py"] + b["py"] - 2 * sc.target_y))
+        return float(np.mean(d)) / width
+
+    def err(an, fd):
+        an, fd = np.asarray(an), np.asarray(fd)
+        return np.abs(an - fd) / np.maximum(np.abs(fd), 1e-3 * np.max(np.abs(fd)))
+
+    o0 = final(st, prm)
+    tr0 = o0["trace"]
+    base = float(np.mean((o0["px"] - sc.target_x) ** 2 + (o0["py"] - sc.target_y) ** 2))
+    np.testing.assert_allclose(base, res["loss"], rtol=1e-14)
+    rng = np.random.default_rng(50)
+    h = 1e-6
+    rows, resampled = [], 0
+    while len(rows) < 31 and resampled < 40:
+        f = ("pref_x", "pref_y")[int(rng.integers(0, 2))]
+        i = int(rng.integers(0, n))
+        sp = {k: v.copy() for k, v in st.items()}
+        sm = {k: v.copy() for k, v in st.items()}
+        sp[f][i] += h
+        sm[f][i] -= h
+        op, om = final(sp, prm), final(sm, prm)
+        if op["trace"] != tr0 or om["trace"] != tr0:
+            resampled += 1
+            continue
+        rows.append((res["g_" + f][i], dloss(op, om, 2 * h)))
+    assert len(rows) == 31, resampled
+    e_pref = err([r[0] for r in rows], [r[1] for r in rows])
+
+    # tau, whole rollout: FP64 perturbation about its FP32 value
+    tau = float(F32(prm.time_horizon))
+    fds = []
+    for ht in (1e-9, 2e-9):
+        op_p = oracle_mod.make_params(prm)
+        op_p.tau = tau + ht
+        op_m = oracle_mod.make_params(prm)
+        op_m.tau = tau - ht
+        a, b = final(st, op_p), final(st, op_m)
+        if a["trace"] == tr0 and b["trace"] == tr0:
+            fds.append(dloss(a, b, 2 * ht))
+    assert fds, "tau: every perturbation crosses a jump"
+    e_tau = float(np.min(np.abs(res["g_tau"] - np.array(fds)) / np.abs(fds)))
+
+    # tau, one step at a time along the oracle's own trajectory
+    fw = oracle_mod.rollout(st, prm, steps, keep_states=True)
+    per_an, per_fd = [], []
+    for t in range(steps):
+        s = dict(st)
+        s.update(fw["states"][t])
+        c = [rng.normal(size=n) for _ in range(4)]
+        g = oracle_mod.step_vjp(s, prm, *c, double_state=True)["g_tau"]
+        vals = []
+        for tt in (tau + 1e-7, tau - 1e-7, tau):
+            op = oracle_mod.make_params(prm)
+            op.tau = tt
+            o = oracle_mod.step_d(s, op)
+            vals.append((sum(float(np.dot(ci, o[k])) for ci, k in zip(c, ("px", "py", "vx", "vy"))),
+                         o["trace"]))
+        if np.array_equal(vals[0][1], vals[2][1]) and np.array_equal(vals[1][1], vals[2][1]):
+            per_an.append(g)
+            per_fd.append((vals[0][0] - vals[1][0]) / 2e-7)
+    e_step = err(per_an, per_fd)
+    print(f"full-shape rollout FD: 31 desired-velocity components ({resampled} resampled) max err "
+          f"{e_pref.max():.2e} median {np.median(e_pref):.2e}; tau {res['g_tau']:.6g} vs FD "
+          f"{[round(x, 3) for x in fds]} (err {e_tau:.1e}); per-step tau {len(per_an)} steps, "
+          f"max err {e_step.max():.2e}")
+    assert e_pref.max() <= 1e-3
+    assert len(per_an) >= 45 and e_step.max() <= 1e-3
+    assert e_tau <= 1e-2
