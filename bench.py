@@ -112,13 +112,26 @@ def algorithmic_ops(work) -> float:
     return float((work.astype(np.float64) * np.asarray(OP_COST, np.float64)[None, :]).sum())
 
 
-def cpu_baseline(state_start, state_end, params, n, steps):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(state_start, state_end, params, n, steps, steps_1t=2):
     """Times the FP64 oracle on this host: `steps` oracle steps from the
     state that opens the timed GPU window, plus one from the state that
-    closes it.  Also returns the oracle's work counters on both states."""
+    closes it, on all threads; then `steps_1t` steps on one thread.  Also
+    returns the oracle's work counters on both states."""
     import numpy as np
     import oracle
     oracle.build(force=False)
+    threads = oracle.set_threads(0)
     t0 = time.perf_counter()
     st = dict(state_start)
     w_start = None
@@ -131,9 +144,22 @@ def cpu_baseline(state_start, state_end, params, n, steps):
             st[k] = o[k].astype(np.float32)
     o_end = oracle.step(state_end, params, want_work=True)
     elapsed = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     rate = n * (steps + 1) / elapsed
-    return rate, elapsed, threads, w_start, o_end["work"]
+    rate_1t = None
+    if steps_1t > 0:
+        oracle.set_threads(1)
+        try:
+            t1 = time.perf_counter()
+            st = dict(state_start)
+            for _ in range(steps_1t):
+                o = oracle.step(st, params)
+                st = dict(st)
+                for k in ("px", "py", "vx", "vy"):
+                    st[k] = o[k].astype(np.float32)
+            rate_1t = n * steps_1t / (time.perf_counter() - t1)
+        finally:
+            oracle.set_threads(threads)
+    return rate, elapsed, threads, w_start, o_end["work"], rate_1t
 
 
 def capture_loop(step_fn, a, b, steps):
@@ -216,6 +242,34 @@ def bench_batched(steps: int):
                                              "mode": tuned["mode"]}}
 
 
+def bench_vehicle_share(steps: int = 100, warmup: int = 10):
+    """Agent-steps/s of the mixed-crowd geometry (66,560 agents) at vehicle
+    shares 0, 1.5, 5 and 50 %: pedestrians and vehicles take the same
+    instructions, so the rate should not depend on the share."""
+    import torch
+    from paper_2008_11578_amd import orca, scenarios
+    rates = {}
+    for share in (0.0, 0.015, 0.05, 0.5):
+        sc = scenarios.c2_vehicle_share(share)
+        st = orca.State.from_arrays(sc)
+        nxt = st.clone()
+        ws = orca.Workspace(sc.n)
+        for _ in range(warmup):
+            orca.step(st, sc.params, ws, out=nxt)
+            st, nxt = nxt, st
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            orca.step(st, sc.params, ws, out=nxt)
+            st, nxt = nxt, st
+        torch.cuda.synchronize()
+        rates[f"{share:g}"] = sc.n * steps / (time.perf_counter() - t0)
+    lo, hi = min(rates.values()), max(rates.values())
+    log("[bench] vehicle share " + ", ".join(f"{k}: {v:.3e}" for k, v in rates.items()))
+    return {"metric": "agent-steps/s, 66,560 agents, by vehicle share", "steps": steps,
+            "rates": rates, "spread": hi / lo - 1.0}
+
+
 def bench_adjoint(reps: int = 3):
     """Differentiable rollout: 16,384 agents, 50 steps, checkpoints every 10:
     forward rollout, then the backward pass (segment replays and
@@ -273,6 +327,8 @@ def main(argv=None):
                     help="graph-captured steps of the 512-scene batched form (0 skips it)")
     ap.add_argument("--no-adjoint", dest="adjoint", action="store_false",
                     help="skip the differentiable-rollout leg")
+    ap.add_argument("--no-vehicle-share", dest="vehicle_share", action="store_false",
+                    help="skip the vehicle-share sweep of the mixed crowd")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) and exit: the "
                          "reference kernel for scaling HBM counters")
@@ -341,13 +397,17 @@ def main(argv=None):
     cpu = None
     ops_per_launch = None
     if args.cpu_steps > 0:
-        rate, el, threads, w0, w1 = cpu_baseline(snap_start, snap_end, params, n, args.cpu_steps)
+        rate, el, threads, w0, w1, rate_1t = cpu_baseline(snap_start, snap_end, params, n,
+                                                           args.cpu_steps)
         ops_per_launch = 0.5 * (algorithmic_ops(w0) + algorithmic_ops(w1))
         cpu = {"value": rate, "unit": "agent-steps/s", "cores": threads, "kind": "oracle",
                "sample": f"{args.cpu_steps} FP64 oracle steps from the state opening the timed "
                          f"GPU window plus 1 from the state closing it, {n} agents "
-                         f"({el:.1f} s)"}
-        log(f"[bench] oracle: {rate:.3e} agent-steps/s on {threads} threads ({el:.1f} s)")
+                         f"({el:.1f} s); single-thread rate from 2 steps of the same state",
+               "single_thread_value": rate_1t, "nproc": os.cpu_count(),
+               "cpu_model": cpu_model()}
+        log(f"[bench] oracle: {rate:.3e} agent-steps/s on {threads} threads ({el:.1f} s), "
+            f"{rate_1t:.3e} on 1 thread")
 
     roof = None
     if ops_per_launch is not None:
@@ -359,10 +419,12 @@ def main(argv=None):
                 "kernel": f"k_step<{params.max_neighbors}>", "kernel_ms": k_ms,
                 "ops_per_launch": ops_per_launch,
                 "hbm_algorithmic_GBs": STEP_BYTES_PER_AGENT * n / (k_ms * 1e-3) / 1e9,
+                "hbm_measured_GBs": (traffic / (k_ms * 1e-3) / 1e9) if traffic else None,
                 "hbm_peak_GBs": HBM_PEAK_GBS, "source_hash": kh}
 
     batched = bench_batched(args.batched_steps) if args.batched_steps > 0 else None
     adjoint = bench_adjoint() if args.adjoint else None
+    vshare = bench_vehicle_share() if args.vehicle_share else None
 
     out = {
         "metric": "agent-steps/sec at 1M agents (ORCA+LP); batched & adjoint steps/sec",
@@ -386,6 +448,7 @@ def main(argv=None):
         "cpu_baseline": cpu,
         "batched": batched,
         "adjoint": adjoint,
+        "vehicle_share": vshare,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -18,6 +18,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "orca_oracle.cpp")
+_SRC_LIFE = os.path.join(_HERE, "lifecycle_oracle.cpp")
 _LIB = os.path.join(_HERE, "liborca_oracle.so")
 K_MAX = 64
 NWORK = 12
@@ -27,10 +28,12 @@ WORK_FIELDS = ("candidates", "in_range", "neighbors", "lp2_checks", "lp2_solves"
 
 def build(force: bool = True) -> str:
     """Compile the oracle with g++ (FP64, no contraction, OpenMP)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    srcs = (_SRC, _SRC_LIFE)
+    if force or not os.path.exists(_LIB) or \
+            any(os.path.getmtime(_LIB) < os.path.getmtime(s) for s in srcs):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fPIC",
-                               "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
+                               "-shared", "-Wall", "-o", tmp, *srcs, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -71,11 +74,65 @@ def lib():
             fn.restype = ctypes.c_int
             fn.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 9 + \
                 [ctypes.POINTER(_OParams)] + [ctypes.c_void_p] * 11
+        L.oracle_arrived.restype = ctypes.c_int
+        L.oracle_arrived.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 6
+        L.oracle_spawn.restype = ctypes.c_int
+        L.oracle_spawn.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 4 + [ctypes.c_int] + \
+            [ctypes.c_void_p] * 4 + [ctypes.c_float, ctypes.c_void_p]
+        L.oracle_set_threads.restype = ctypes.c_int
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_step_batched.restype = ctypes.c_int
         L.oracle_step_batched.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 10 + \
             [ctypes.c_void_p] + [ctypes.c_void_p] * 6
         _lib = L
     return _lib
+
+
+def arrived(state) -> np.ndarray:
+    """1 where an agent's goal (its pref input) lies within its disc."""
+    g = state.get if isinstance(state, dict) else (lambda k: getattr(state, k))
+    a = [np.ascontiguousarray(g(k), dtype=np.float32) for k in ("px", "py", "pref_x", "pref_y",
+                                                                "radius")]
+    n = a[0].shape[0]
+    out = np.zeros(n, np.uint8)
+    if lib().oracle_arrived(n, *[x.ctypes.data for x in a], out.ctypes.data) != 0:
+        raise ValueError("oracle_arrived failed")
+    return out
+
+
+def remove_arrived(state) -> dict:
+    """The state without the agents that reached their goal, survivors in
+    their order; also 'old_to_new' (new index or -1)."""
+    g = state.get if isinstance(state, dict) else (lambda k: getattr(state, k))
+    keep = arrived(state) == 0
+    out = {k: np.asarray(g(k))[keep] for k in _STATE + ("cls",)}
+    o2n = np.full(keep.shape[0], -1, np.int32)
+    o2n[keep] = np.arange(int(keep.sum()), dtype=np.int32)
+    out["old_to_new"] = o2n
+    return out
+
+
+def spawn(state, cand, t_clear: float) -> np.ndarray:
+    """Acceptance (0/1 per candidate, in order) of spawn candidates
+    cand = dict(px, py, radius, max_speed) against the agents of `state`
+    and the candidates accepted before each one."""
+    g = state.get if isinstance(state, dict) else (lambda k: getattr(state, k))
+    a = [np.ascontiguousarray(g(k), dtype=np.float32) for k in ("px", "py", "radius", "max_speed")]
+    c = [np.ascontiguousarray(cand[k], dtype=np.float32) for k in ("px", "py", "radius",
+                                                                   "max_speed")]
+    n, nc = a[0].shape[0], c[0].shape[0]
+    acc = np.zeros(nc, np.uint8)
+    rc = lib().oracle_spawn(n, *[x.ctypes.data for x in a], nc, *[x.ctypes.data for x in c],
+                            float(np.float32(t_clear)), acc.ctypes.data)
+    if rc < 0:
+        raise ValueError("oracle_spawn failed")
+    return acc
+
+
+def set_threads(t: int = 0) -> int:
+    """Sets the oracle's OpenMP thread count when t > 0; returns the count in
+    effect."""
+    return int(lib().oracle_set_threads(int(t)))
 
 
 def _f32d(x) -> float:

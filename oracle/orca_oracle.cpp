@@ -56,6 +56,8 @@
 #include <cstring>
 #include <vector>
 
+#include <omp.h>
+
 #define ORACLE_K_MAX 64
 #define ORACLE_NWORK 12
 
@@ -851,6 +853,14 @@ struct Widened {
 extern "C" {
 
 typedef OParams oparams;
+
+/* Sets the OpenMP thread count of later calls when t > 0; returns the count
+ * now in effect. */
+int oracle_set_threads(int t)
+{
+    if (t > 0) omp_set_num_threads(t);
+    return omp_get_max_threads();
+}
 
 int oracle_halfplane(double pax, double pay, double vax, double vay, double ra, double pbx,
                      double pby, double vbx, double vby, double rb, double f, double tau,

@@ -98,40 +98,48 @@ __device__ __forceinline__ bool entry_less(uint64_t ea, uint64_t eb, const float
     return __float_as_int(ca.z) < __float_as_int(cb.z);
 }
 
-// Visits the cell-order candidates [ra, rb) in order, keeping four
-// independent loads in flight per lane.
+// Candidates loaded per group by one lane.
+#ifndef ORCA_SCAN_UNROLL
+#define ORCA_SCAN_UNROLL 8
+#endif
+constexpr int kScanUnroll = ORCA_SCAN_UNROLL;
+
+// Visits the cell-order candidates [ra, rb) (ra < rb) in order, in groups of
+// kScanUnroll independent loads; the last group re-reads candidate rb - 1 for
+// its missing members and skips them, so there is no remainder loop.
 template <class F>
 __device__ __forceinline__ void scan_range(const float4 *__restrict__ s0, uint32_t ra, uint32_t rb,
                                            F &&visit)
 {
-    uint32_t t = ra;
-    for (; t + 4 <= rb; t += 4) {
-        const float4 c0 = s0[t], c1 = s0[t + 1], c2 = s0[t + 2], c3 = s0[t + 3];
-        visit(c0, t);
-        visit(c1, t + 1);
-        visit(c2, t + 2);
-        visit(c3, t + 3);
+    for (uint32_t t = ra; t < rb; t += kScanUnroll) {
+        float4 c[kScanUnroll];
+#pragma unroll
+        for (int q = 0; q < kScanUnroll; ++q) c[q] = s0[min(t + (uint32_t)q, rb - 1u)];
+#pragma unroll
+        for (int q = 0; q < kScanUnroll; ++q)
+            if (t + (uint32_t)q < rb) visit(c[q], t + (uint32_t)q);
     }
-    for (; t < rb; ++t) visit(s0[t], t);
 }
 
-// Grid rows that can hold an agent within R_n of y.
-__device__ __forceinline__ void row_span(const GridMeta &g, double yd, int &ya, int &yb)
+// Grid rows that can hold an agent within sqrt(r2) of y (r2 <= R_n^2).
+__device__ __forceinline__ void row_span(const GridMeta &g, double yd, double r2, int &ya, int &yb)
 {
-    const double rn = sqrt(g.rn2);
-    const double ua = floor((yd - rn - (double)g.y0) * g.inv_cs - 1e-6);
-    const double ub = floor((yd + rn - (double)g.y0) * g.inv_cs + 1e-6);
+    const double r = sqrt(r2);
+    const double ua = floor((yd - r - (double)g.y0) * g.inv_cs - 1e-6);
+    const double ub = floor((yd + r - (double)g.y0) * g.inv_cs + 1e-6);
     ya = (int)fmin(fmax(ua, 0.0), (double)(g.ny - 1));
     yb = (int)fmin(fmax(ub, 0.0), (double)(g.ny - 1));
 }
 
-// Cell-order range of row yy clipped to the chord; false when empty.
+// Cell-order range of row yy clipped to the chord of the circle of squared
+// radius r2 around (xd, yd); false when empty.
 __device__ __forceinline__ bool row_range(const GridMeta &g, const uint32_t *__restrict__ start,
-                                          double xd, double yd, int yy, uint32_t &a, uint32_t &b)
+                                          double xd, double yd, double r2, int yy, uint32_t &a,
+                                          uint32_t &b)
 {
     const double ylo = (double)g.y0 + (double)yy * g.cs_d;
     const double dy = fmax(fmax(ylo - yd, yd - (ylo + g.cs_d)) - 1e-6 * g.cs_d, 0.0);
-    const double h2 = g.rn2 - dy * dy;
+    const double h2 = r2 - dy * dy;
     if (!(h2 > 0.0)) return false;
     const double hw = sqrt(h2);
     const double ua = floor((xd - hw - (double)g.x0) * g.inv_cs - 1e-6);
@@ -145,6 +153,54 @@ __device__ __forceinline__ bool row_range(const GridMeta &g, const uint32_t *__r
     return a < b;
 }
 
+// Bitonic sorting network over N (a power of two) 64-bit keys held in
+// registers, ascending; every index is a compile-time constant.
+template <int K>
+struct SortNet {
+    static constexpr int N = K <= 8 ? 16 : (K <= 24 ? 32 : 64);
+};
+
+template <int N>
+__device__ __forceinline__ void bitonic_sort(uint64_t (&e)[N])
+{
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const uint64_t a = e[i], b = e[l];
+                    const bool sw = ((i & k) == 0) ? (b < a) : (a < b);
+                    e[i] = sw ? b : a;
+                    e[l] = sw ? a : b;
+                }
+            }
+        }
+    }
+}
+
+// Visits every candidate in the grid rows and chords of the circle of
+// squared radius r2 around (xd, yd), row by row; the next row's range (two
+// loads from `start`) is requested before the current row is scanned.
+template <class F>
+__device__ __forceinline__ void scan_disc(const GridMeta &g, const uint32_t *__restrict__ start,
+                                          const float4 *__restrict__ s0, double xd, double yd,
+                                          double r2, F &&visit)
+{
+    int ya, yb;
+    row_span(g, yd, r2, ya, yb);
+    uint32_t na = 0, nb = 0;
+    bool nok = row_range(g, start, xd, yd, r2, ya, na, nb);
+    for (int yy = ya; yy <= yb; ++yy) {
+        const uint32_t ra = na, rb = nb;
+        const bool ok = nok;
+        if (yy < yb) nok = row_range(g, start, xd, yd, r2, yy + 1, na, nb);
+        if (ok) scan_range(s0, ra, rb, visit);
+    }
+}
+
 // Selects the (at most K) nearest agents of the lane into entries [0, m) of
 // its LDS buffer, ascending; returns m.
 template <int K, int BLOCK>
@@ -155,26 +211,23 @@ __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
     constexpr int kCap = KnnShape<K>::kCap;
     const double xd = xi, yd = yi;
     const double bscale = (double)kBins / g.rn2;
-    int ya, yb;
-    row_span(g, yd, ya, yb);
-
-    // pass 1: per-bin counts
+    // pass 1: per-bin counts.  The lane's own agent is counted too (it is
+    // always scanned, with key 0, in bin 0) and taken out afterwards, which
+    // keeps the index test out of this loop.
     uint64_t hlo = 0, hhi = 0;
     uint32_t total = 0;
-    for (int yy = ya; yy <= yb; ++yy) {
-        uint32_t ra, rb;
-        if (!row_range(g, start, xd, yd, yy, ra, rb)) continue;
-        scan_range(s0, ra, rb, [&](const float4 &c, uint32_t) {
-            const double key = nb_key(xi, yi, c.x, c.y);
-            if (key < g.rn2 && __float_as_int(c.z) != self) {
-                const int bin = min((int)(key * bscale), kBins - 1);
-                const uint64_t inc = 1ull << ((bin & 7) * 8);
-                hlo += bin < 8 ? inc : 0ull;
-                hhi += bin < 8 ? 0ull : inc;
-                ++total;
-            }
-        });
-    }
+    scan_disc(g, start, s0, xd, yd, g.rn2, [&](const float4 &c, uint32_t) {
+        const double key = nb_key(xi, yi, c.x, c.y);
+        if (key < g.rn2) {
+            const int bin = min((int)(key * bscale), kBins - 1);
+            const uint64_t inc = 1ull << ((bin & 7) * 8);
+            hlo += bin < 8 ? inc : 0ull;
+            hhi += bin < 8 ? 0ull : inc;
+            ++total;
+        }
+    });
+    hlo -= 1ull;
+    total -= 1u;
 
     // threshold bin and bucket offsets
     uint64_t olo = 0, ohi = 0;
@@ -198,42 +251,69 @@ __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
     if (!found) take = total;
 
     if (total <= 255u && take <= (uint32_t)kCap) {
-        // pass 2: bucket scatter of bins <= b*
-        for (int yy = ya; yy <= yb; ++yy) {
-            uint32_t ra, rb;
-            if (!row_range(g, start, xd, yd, yy, ra, rb)) continue;
-            scan_range(s0, ra, rb, [&](const float4 &c, uint32_t t) {
-                const double key = nb_key(xi, yi, c.x, c.y);
-                if (key < g.rn2 && __float_as_int(c.z) != self) {
-                    const int bin = min((int)(key * bscale), kBins - 1);
-                    if (bin <= bstar) {
-                        const int sh = (bin & 7) * 8;
-                        const uint32_t slot = (uint32_t)(((bin < 8 ? olo : ohi) >> sh) & 0xffull);
-                        const uint64_t inc = 1ull << sh;
-                        olo += bin < 8 ? inc : 0ull;
-                        ohi += bin < 8 ? 0ull : inc;
-                        if (slot < (uint32_t)kCap)  // always true: both passes count alike
-                            buf[buf_idx<BLOCK>((int)slot, tid)] = pack_entry(key, t);
-                    }
+        // pass 2: bucket scatter of bins <= b*.  Every key in those bins is
+        // below (b* + 1) R_n^2 / kBins, so only rows and chords of that
+        // smaller circle are visited (with a relative margin far above the
+        // rounding of key * bscale).
+        const double r2 = bstar + 1 < kBins
+                              ? (double)(bstar + 1) * (g.rn2 / (double)kBins) * (1.0 + 1e-9)
+                              : g.rn2;
+        scan_disc(g, start, s0, xd, yd, r2, [&](const float4 &c, uint32_t t) {
+            const double key = nb_key(xi, yi, c.x, c.y);
+            if (key < g.rn2 && __float_as_int(c.z) != self) {
+                const int bin = min((int)(key * bscale), kBins - 1);
+                if (bin <= bstar) {
+                    const int sh = (bin & 7) * 8;
+                    const uint32_t slot = (uint32_t)(((bin < 8 ? olo : ohi) >> sh) & 0xffull);
+                    const uint64_t inc = 1ull << sh;
+                    olo += bin < 8 ? inc : 0ull;
+                    ohi += bin < 8 ? 0ull : inc;
+                    if (slot < (uint32_t)kCap)  // always true: both passes count alike
+                        buf[buf_idx<BLOCK>((int)slot, tid)] = pack_entry(key, t);
                 }
-            });
-        }
-        // order inside the buckets (bins are already in order)
-        for (int p = 1; p < (int)take; ++p) {
-            const uint64_t e = buf[buf_idx<BLOCK>(p, tid)];
-            int q = p - 1;
-            while (q >= 0) {
-                const uint64_t f = buf[buf_idx<BLOCK>(q, tid)];
-                if (!entry_less(e, f, s0, xi, yi)) break;
-                buf[buf_idx<BLOCK>(q + 1, tid)] = f;
-                --q;
             }
-            buf[buf_idx<BLOCK>(q + 1, tid)] = e;
+        });
+        // order inside the buckets (bins are already in order): a sorting
+        // network in registers when the entries fit it, which orders them by
+        // (FP32 key, cell-order position); an FP32-key tie among the entries
+        // that decide the result needs the (FP64 key, caller index) order of
+        // entry_less, left to the insertion pass below
+        constexpr int N = SortNet<K>::N;
+        bool sorted = false;
+        if (take <= (uint32_t)N) {
+            uint64_t e[N];
+#pragma unroll
+            for (int p = 0; p < N; ++p) e[p] = p < (int)take ? buf[buf_idx<BLOCK>(p, tid)] : ~0ull;
+            bitonic_sort<N>(e);
+            bool tie = false;
+#pragma unroll
+            for (int p = 0; p + 1 < N; ++p)
+                tie = tie || (p < K && p + 1 < (int)take &&
+                              (uint32_t)(e[p] >> 32) == (uint32_t)(e[p + 1] >> 32));
+#pragma unroll
+            for (int p = 0; p < N; ++p)
+                if (p < (int)take) buf[buf_idx<BLOCK>(p, tid)] = e[p];
+            sorted = !tie;
+        }
+        if (!sorted) {
+            for (int p = 1; p < (int)take; ++p) {
+                const uint64_t e = buf[buf_idx<BLOCK>(p, tid)];
+                int q = p - 1;
+                while (q >= 0) {
+                    const uint64_t f = buf[buf_idx<BLOCK>(q, tid)];
+                    if (!entry_less(e, f, s0, xi, yi)) break;
+                    buf[buf_idx<BLOCK>(q + 1, tid)] = f;
+                    --q;
+                }
+                buf[buf_idx<BLOCK>(q + 1, tid)] = e;
+            }
         }
         return take < (uint32_t)K ? (int)take : K;
     }
 
     // fallback: repeated minimum over all candidates, strictly above the last pick
+    int ya, yb;
+    row_span(g, yd, g.rn2, ya, yb);
     double lk = -1.0;
     int lj = -1;
     int m = 0;
@@ -243,7 +323,7 @@ __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
         uint32_t bt = 0;
         for (int yy = ya; yy <= yb; ++yy) {
             uint32_t ra, rb;
-            if (!row_range(g, start, xd, yd, yy, ra, rb)) continue;
+            if (!row_range(g, start, xd, yd, g.rn2, yy, ra, rb)) continue;
             for (uint32_t t = ra; t < rb; ++t) {
                 const float4 c = s0[t];
                 const int j = __float_as_int(c.z);

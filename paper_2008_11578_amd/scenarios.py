@@ -152,6 +152,16 @@ def c2_mixed(seed: int = 2) -> Scenario:
                           steps=200, name="c2_mixed_66560")
 
 
+def c2_vehicle_share(share: float, seed: int = 2) -> Scenario:
+    """The mixed-crowd geometry (66,560 agents in 500 x 500 m, same
+    parameters) with round(share * 66,560) of the agents vehicles."""
+    n = 65536 + 1024
+    nv = int(round(share * n))
+    p = Params(dt=0.05, time_horizon=2.0, neighbor_dist=5.0, max_neighbors=16)
+    return uniform_square(n, 500.0, seed, n_vehicles=nv, params=p, steps=200,
+                          name=f"c2_vehicle_share_{share:g}")
+
+
 def crossing(side_count: int, side: float, seed: int, *, jitter: float = 0.04,
              params: Optional[Params] = None, steps: int = 1,
              name: str = "crossing") -> Scenario:

@@ -59,3 +59,12 @@ def test_c5_rollout_targets():
     np.testing.assert_allclose(sp, 1.4, rtol=1e-6)
     assert (sp < sc.max_speed).all()
     assert sc.target_x is not None and sc.target_x.shape == (512,)
+
+
+def test_c2_vehicle_share_same_geometry():
+    base = scenarios.c2_vehicle_share(0.0)
+    half = scenarios.c2_vehicle_share(0.5)
+    assert base.n == half.n == 66560
+    assert int(base.cls.sum()) == 0 and int(half.cls.sum()) == 33280
+    # vehicles are the last agents; the pedestrians' positions do not depend on the share
+    np.testing.assert_array_equal(base.px[:1000], half.px[:1000])
