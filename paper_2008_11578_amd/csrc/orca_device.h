@@ -55,13 +55,14 @@ __device__ __forceinline__ double nb_key(float xi, float yi, float xj, float yj)
 // are 8-bit fields of two 64-bit registers.  The first bin b* at which the
 // running count reaches k is the threshold: every candidate of a lower bin is
 // among the k nearest and the rest of the k nearest lie in bin b*.
-// Pass 2 scatters the candidates of bins <= b* into the lane's LDS column in
-// bin order (bucket offsets are 8-bit fields too), and an insertion pass
-// orders each bucket.  Buffer entries are (float(key) bits << 32 | cell-order
+// Pass 2 visits only the circle that holds bins <= b* and appends their
+// candidates to the lane's LDS column; a bitonic network over registers then
+// orders them.  Buffer entries are (float(key) bits << 32 | cell-order
 // position): a strict order of the FP32-rounded keys implies the same order
-// of the FP64 keys (rounding is monotone); equal FP32 keys are resolved by
-// recomputing the FP64 keys and then the caller indices.
-// A lane whose counts could overflow (> 255 in range) or whose buckets do
+// of the FP64 keys (rounding is monotone); equal FP32 keys among the entries
+// that decide the result are resolved by an insertion pass that recomputes
+// the FP64 keys and then compares the caller indices.
+// A lane whose counts could overflow (> 255 in range) or whose candidates do
 // not fit the buffer selects by repeated minimum instead (exact, slower).
 // ---------------------------------------------------------------------------
 constexpr int kBins = 16;
@@ -229,19 +230,13 @@ __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
     hlo -= 1ull;
     total -= 1u;
 
-    // threshold bin and bucket offsets
-    uint64_t olo = 0, ohi = 0;
+    // threshold bin b*: the first bin at which the cumulative count reaches K
     uint32_t cum = 0, take = 0;
     int bstar = kBins - 1;
     bool found = false;
 #pragma unroll
     for (int b = 0; b < kBins; ++b) {
-        const uint32_t cnt = (uint32_t)(((b < 8 ? hlo : hhi) >> ((b & 7) * 8)) & 0xffull);
-        if (b < 8)
-            olo |= (uint64_t)(cum & 0xffu) << (b * 8);
-        else
-            ohi |= (uint64_t)(cum & 0xffu) << ((b - 8) * 8);
-        cum += cnt;
+        cum += (uint32_t)(((b < 8 ? hlo : hhi) >> ((b & 7) * 8)) & 0xffull);
         if (!found && cum >= (uint32_t)K) {
             found = true;
             bstar = b;
@@ -251,33 +246,28 @@ __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
     if (!found) take = total;
 
     if (total <= 255u && take <= (uint32_t)kCap) {
-        // pass 2: bucket scatter of bins <= b*.  Every key in those bins is
-        // below (b* + 1) R_n^2 / kBins, so only rows and chords of that
-        // smaller circle are visited (with a relative margin far above the
-        // rounding of key * bscale).
-        const double r2 = bstar + 1 < kBins
-                              ? (double)(bstar + 1) * (g.rn2 / (double)kBins) * (1.0 + 1e-9)
-                              : g.rn2;
+        // pass 2: collect the candidates of bins <= b*, in scan order.  For
+        // b* below the last bin, bin <= b* is exactly key * bscale < b* + 1
+        // (truncation of a non-negative value), so both passes count alike.
+        // Every such key is below (b* + 1) R_n^2 / kBins, so only rows and
+        // chords of that smaller circle are visited (with a relative margin
+        // far above the rounding of key * bscale).
+        const bool last = bstar + 1 >= kBins;
+        const double bnext = last ? INFINITY : (double)(bstar + 1);
+        const double r2 = last ? g.rn2 : (double)(bstar + 1) * (g.rn2 / (double)kBins) * (1.0 + 1e-9);
+        uint32_t slot = 0;
         scan_disc(g, start, s0, xd, yd, r2, [&](const float4 &c, uint32_t t) {
             const double key = nb_key(xi, yi, c.x, c.y);
-            if (key < g.rn2 && __float_as_int(c.z) != self) {
-                const int bin = min((int)(key * bscale), kBins - 1);
-                if (bin <= bstar) {
-                    const int sh = (bin & 7) * 8;
-                    const uint32_t slot = (uint32_t)(((bin < 8 ? olo : ohi) >> sh) & 0xffull);
-                    const uint64_t inc = 1ull << sh;
-                    olo += bin < 8 ? inc : 0ull;
-                    ohi += bin < 8 ? 0ull : inc;
-                    if (slot < (uint32_t)kCap)  // always true: both passes count alike
-                        buf[buf_idx<BLOCK>((int)slot, tid)] = pack_entry(key, t);
-                }
+            if (key < g.rn2 && key * bscale < bnext && __float_as_int(c.z) != self) {
+                if (slot < (uint32_t)kCap)  // always true: both passes count alike
+                    buf[buf_idx<BLOCK>((int)slot, tid)] = pack_entry(key, t);
+                ++slot;
             }
         });
-        // order inside the buckets (bins are already in order): a sorting
-        // network in registers when the entries fit it, which orders them by
-        // (FP32 key, cell-order position); an FP32-key tie among the entries
-        // that decide the result needs the (FP64 key, caller index) order of
-        // entry_less, left to the insertion pass below
+        // order: a sorting network in registers when the entries fit it,
+        // which orders them by (FP32 key, cell-order position); an FP32-key
+        // tie among the entries that decide the result needs the (FP64 key,
+        // caller index) order of entry_less, left to the insertion pass below
         constexpr int N = SortNet<K>::N;
         bool sorted = false;
         if (take <= (uint32_t)N) {
