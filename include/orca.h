@@ -189,6 +189,68 @@ int orca_step_backward(const orca_agents_in *in, int32_t n, const orca_params *p
                        const orca_cotangents *g1, const orca_cotangents_out *g0, void *ws,
                        size_t ws_bytes, hipStream_t stream);
 
+/* ---- Agent lifecycle (Sec. 4, first experiment) -------------------------
+ * In the crossing experiments agents are spawned in start regions at points
+ * that keep clear of everyone for a while, walk to a goal in the matching
+ * end region, and leave the simulation once they reach it.  The two entry
+ * points below implement the leaving and the entering between steps. */
+
+/* A writable agent state (device pointers, length = capacity, caller order). */
+typedef struct {
+    float *px, *py, *vx, *vy, *pref_x, *pref_y, *radius, *max_speed;
+    uint8_t *cls;
+} orca_agents_buf;
+
+/* Largest number of spawn candidates one orca_spawn call accepts. */
+#define ORCA_SPAWN_MAX 16384
+
+/* Workspace bytes of orca_remove_arrived and orca_spawn for up to n agents
+ * and n_cand spawn candidates (zero-filled once, like every workspace). */
+size_t orca_lifecycle_workspace_bytes(int32_t n, int32_t n_cand);
+
+/* Removes every agent whose goal (pref_x, pref_y, read as a goal position)
+ * lies inside or on its disc, |g - p|^2 <= r^2 (evaluated in double from the
+ * FP32 values, each operation rounded separately), and writes the others, in
+ * their order, to out[0 .. *n_alive).  out must not overlap in.  n_alive
+ * (DEVICE, one int32) receives the count; old_to_new (DEVICE, n entries,
+ * nullable) the new index of every agent or -1.  With n == 0 the agent
+ * arrays may be null and *n_alive is set to 0. */
+int orca_remove_arrived(const orca_agents_in *in, const orca_agents_buf *out, int32_t n,
+                        int32_t *n_alive, int32_t *old_to_new, void *ws, size_t ws_bytes,
+                        hipStream_t stream);
+
+/* Spawns agents.  Candidates cand[0 .. n_cand) (device arrays; all nine
+ * fields, as the new agents' initial state) are taken in their order; a
+ * candidate enters when, for every agent present -- the n agents of `state`
+ * and the candidates that entered before it --
+ *     |p_c - p_j|^2 >= D^2,   D = (r_c + r_j) + t_clear (s_c + s_j)
+ * (s = max_speed; double from the FP32 values, operations rounded
+ * separately in this order): the two cannot touch within t_clear seconds
+ * even heading straight for each other at full speed.  Accepted candidates
+ * are appended, in order, at state[n ...]; capacity (the length of the state
+ * arrays) must be at least n + n_cand.  n_total (DEVICE, one int32) receives
+ * n plus the number accepted; accepted (DEVICE, n_cand bytes, nullable) the
+ * decision per candidate.  n_cand <= ORCA_SPAWN_MAX; t_clear >= 0.  The
+ * candidate arrays may be null when n_cand == 0, the state arrays when
+ * n + n_cand == 0; *n_total is written in every case. */
+int orca_spawn(const orca_agents_buf *state, int32_t n, int32_t capacity,
+               const orca_agents_in *cand, int32_t n_cand, float t_clear, int32_t *n_total,
+               uint8_t *accepted, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Workspace bytes of orca_overlap_stats for n agents. */
+size_t orca_overlap_workspace_bytes(int32_t n);
+
+/* Collision statistics of a crowd (the measure of the crossing experiments,
+ * Sec. 4), over the pairs closer than `reach` (|p_i - p_j|^2 < reach^2;
+ * reach >= twice the largest radius covers every overlap), in double from
+ * the FP32 positions and radii: out[0] = pairs whose discs overlap,
+ * |p_i - p_j|^2 < (r_i + r_j)^2; out[1] = agents in at least one such pair;
+ * out[2] = the smallest clearance |p_i - p_j| - (r_i + r_j) (+inf when no
+ * pair is that close).  out: DEVICE, 3 doubles, written in stream order
+ * (also for n == 0).  reach > 0. */
+int orca_overlap_stats(const orca_agents_in *in, int32_t n, float reach, double *out, void *ws,
+                       size_t ws_bytes, hipStream_t stream);
+
 /* Human-readable text for a status code (static storage). */
 const char *orca_status_string(int code);
 

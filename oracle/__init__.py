@@ -79,6 +79,9 @@ def lib():
         L.oracle_spawn.restype = ctypes.c_int
         L.oracle_spawn.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 4 + [ctypes.c_int] + \
             [ctypes.c_void_p] * 4 + [ctypes.c_float, ctypes.c_void_p]
+        L.oracle_overlap_stats.restype = ctypes.c_int
+        L.oracle_overlap_stats.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 3 + \
+            [ctypes.c_float, ctypes.c_void_p]
         L.oracle_set_threads.restype = ctypes.c_int
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_step_batched.restype = ctypes.c_int
@@ -127,6 +130,19 @@ def spawn(state, cand, t_clear: float) -> np.ndarray:
     if rc < 0:
         raise ValueError("oracle_spawn failed")
     return acc
+
+
+def overlap_stats(state, reach: float) -> dict:
+    """Overlapping pairs, agents in an overlap, and the smallest clearance
+    |p_i - p_j| - (r_i + r_j) over the pairs closer than `reach` (brute
+    force)."""
+    g = state.get if isinstance(state, dict) else (lambda k: getattr(state, k))
+    a = [np.ascontiguousarray(g(k), dtype=np.float32) for k in ("px", "py", "radius")]
+    out = np.zeros(3)
+    if lib().oracle_overlap_stats(a[0].shape[0], *[x.ctypes.data for x in a],
+                                  float(np.float32(reach)), out.ctypes.data):
+        raise ValueError("oracle_overlap_stats failed")
+    return {"pairs": int(out[0]), "agents": int(out[1]), "min_clearance": float(out[2])}
 
 
 def set_threads(t: int = 0) -> int:

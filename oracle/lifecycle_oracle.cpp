@@ -23,7 +23,9 @@
  *    straight for each other at full speed.  Both sides are in double from
  *    FP32 values, operations rounded separately in the order written.
  */
+#include <cmath>
 #include <cstdint>
+#include <vector>
 
 namespace {
 
@@ -77,6 +79,46 @@ int oracle_spawn(int n, const float *px, const float *py, const float *radius,
         count += ok ? 1 : 0;
     }
     return count;
+}
+
+} /* extern "C" */
+
+extern "C" {
+
+/* Overlap statistics of a crowd (the collision measure of the crossing
+ * experiments, Sec. 4) over the pairs i < j closer than `reach`
+ * (|p_i - p_j|^2 < reach^2, double from FP32 values; reach >= 2 max r
+ * covers every overlap): out[0] = pairs whose discs overlap,
+ * |p_i - p_j|^2 < (r_i + r_j)^2; out[1] = agents in at least one of them;
+ * out[2] = the smallest clearance |p_i - p_j| - (r_i + r_j) (+inf when no
+ * pair is that close).  Brute force over all pairs. */
+int oracle_overlap_stats(int n, const float *px, const float *py, const float *radius,
+                         float reach, double *out)
+{
+    if (n < 0) return -1;
+    const double q = (double)reach;
+    int64_t pairs = 0, agents = 0;
+    double gap = INFINITY;
+    std::vector<uint8_t> hit((size_t)n, 0);
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            const double dx = (double)px[j] - (double)px[i];
+            const double dy = (double)py[j] - (double)py[i];
+            const double d2 = dx * dx + dy * dy;
+            if (!(d2 < q * q)) continue;
+            const double rr = (double)radius[i] + (double)radius[j];
+            if (d2 < rr * rr) {
+                ++pairs;
+                hit[i] = hit[j] = 1;
+            }
+            const double g = std::sqrt(d2) - rr;
+            if (g < gap) gap = g;
+        }
+    for (int i = 0; i < n; ++i) agents += hit[i];
+    out[0] = (double)pairs;
+    out[1] = (double)agents;
+    out[2] = gap;
+    return 0;
 }
 
 } /* extern "C" */

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liborca.so")
-SOURCES = ["grid.hip", "step.hip", "batch.hip", "adjoint.hip", "capi.hip"]
+SOURCES = ["grid.hip", "step.hip", "batch.hip", "adjoint.hip", "lifecycle.hip", "capi.hip"]
 HEADERS = ["orca_internal.h", "orca_device.h", os.path.join("..", "..", "include", "orca.h")]
 ARCH = os.environ.get("ORCA_OFFLOAD_ARCH", "gfx950")
 

@@ -41,7 +41,7 @@ Layout make_layout(int64_t n, int64_t n_scenes, int64_t max_cells)
     L.tiles = o;
     o = align_up(o + sizeof(uint32_t) * (size_t)(L.n_tiles + 1));
     L.s0 = o;
-    o = align_up(o + sizeof(float4) * (size_t)n);
+    o = align_up(o + sizeof(float4) * (size_t)(n + kScanPad));
     L.s1 = o;
     o = align_up(o + sizeof(float4) * (size_t)n);
     L.total = o;
@@ -146,6 +146,18 @@ int check_out(const orca_agents_out *out)
     if (!out || !out->px || !out->py || !out->vx || !out->vy) return ORCA_EINVAL;
     return ORCA_OK;
 }
+
+int check_buf(const orca_agents_buf *b)
+{
+    if (!b || !b->px || !b->py || !b->vx || !b->vy || !b->pref_x || !b->pref_y || !b->radius ||
+        !b->max_speed || !b->cls)
+        return ORCA_EINVAL;
+    return ORCA_OK;
+}
+
+// Workspace of the lifecycle entry points: the grid of n agents, then the
+// lifecycle buffers.
+Layout life_layout(int64_t n) { return make_layout(n > 0 ? n : 1, 0, 0); }
 
 // Cell count that keeps the grid within what the 32-bit indices address.
 constexpr int64_t kMaxCellsCap = (int64_t)1 << 30;
@@ -287,6 +299,70 @@ int orca_step_backward(const orca_agents_in *in, int32_t n, const orca_params *p
     if (launch_grid_build(*in, n, *params, L, w, stream) != hipSuccess) return ORCA_EHIP;
     if (launch_adjoint(*in, n, *params, L, w, b, g1->px, g1->py, g1->vx, g1->vy, g0->px, g0->py,
                        g0->vx, g0->vy, g0->pref_x, g0->pref_y, g0->tau, stream) != hipSuccess)
+        return ORCA_EHIP;
+    return ORCA_OK;
+}
+
+size_t orca_lifecycle_workspace_bytes(int32_t n, int32_t n_cand)
+{
+    if (n < 0 || n_cand < 0) return 0;
+    return align_up(life_layout(n).total) + lifecycle_extra_bytes(n, n_cand);
+}
+
+int orca_remove_arrived(const orca_agents_in *in, const orca_agents_buf *out, int32_t n,
+                        int32_t *n_alive, int32_t *old_to_new, void *ws, size_t ws_bytes,
+                        hipStream_t stream)
+{
+    if (n < 0 || !n_alive || !ws) return ORCA_EINVAL;
+    if (n > 0 && (check_in(in) != ORCA_OK || check_buf(out) != ORCA_OK)) return ORCA_EINVAL;
+    if (ws_bytes < orca_lifecycle_workspace_bytes(n, 0)) return ORCA_EWORKSPACE;
+    void *extra = (char *)ws + align_up(life_layout(n).total);
+    const orca_agents_in no_in{};
+    const orca_agents_buf no_out{};
+    if (launch_remove_arrived(n > 0 ? *in : no_in, n > 0 ? *out : no_out, n, n_alive, old_to_new,
+                              extra, stream) != hipSuccess)
+        return ORCA_EHIP;
+    return ORCA_OK;
+}
+
+int orca_spawn(const orca_agents_buf *state, int32_t n, int32_t capacity,
+               const orca_agents_in *cand, int32_t n_cand, float t_clear, int32_t *n_total,
+               uint8_t *accepted, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (n < 0 || n_cand < 0 || n_cand > ORCA_SPAWN_MAX || !n_total || !ws) return ORCA_EINVAL;
+    if ((int64_t)capacity < (int64_t)n + (int64_t)n_cand) return ORCA_EINVAL;
+    if (!(t_clear >= 0.0f) || !isfinite(t_clear)) return ORCA_EINVAL;
+    if (n + n_cand > 0 && check_buf(state) != ORCA_OK) return ORCA_EINVAL;
+    if (n_cand > 0 && check_in(cand) != ORCA_OK) return ORCA_EINVAL;
+    if (ws_bytes < orca_lifecycle_workspace_bytes(n, n_cand)) return ORCA_EWORKSPACE;
+    const Layout L = life_layout(n);
+    const Work w = bind(L, ws);
+    void *extra = (char *)ws + align_up(L.total);
+    const orca_agents_in no_cand{};
+    const orca_agents_buf no_state{};
+    if (launch_spawn(n + n_cand > 0 ? *state : no_state, n, n_cand > 0 ? *cand : no_cand, n_cand,
+                     t_clear, n_total, accepted, L, w, extra, stream) != hipSuccess)
+        return ORCA_EHIP;
+    return ORCA_OK;
+}
+
+size_t orca_overlap_workspace_bytes(int32_t n)
+{
+    if (n < 0) return 0;
+    return align_up(life_layout(n).total) + overlap_extra_bytes(n);
+}
+
+int orca_overlap_stats(const orca_agents_in *in, int32_t n, float reach, double *out, void *ws,
+                       size_t ws_bytes, hipStream_t stream)
+{
+    if (n < 0 || !out || !ws || !finite_pos(reach)) return ORCA_EINVAL;
+    if (n > 0 && check_in(in) != ORCA_OK) return ORCA_EINVAL;
+    if (ws_bytes < orca_overlap_workspace_bytes(n)) return ORCA_EWORKSPACE;
+    const Layout L = life_layout(n);
+    const Work w = bind(L, ws);
+    void *extra = (char *)ws + align_up(L.total);
+    if (launch_overlap_stats(n > 0 ? *in : orca_agents_in{}, n, reach, out, L, w, extra, stream) !=
+        hipSuccess)
         return ORCA_EHIP;
     return ORCA_OK;
 }

@@ -38,8 +38,10 @@ __global__ __launch_bounds__(kBlock) void k_bbox_partial(const float *__restrict
 __global__ __launch_bounds__(kBlock) void k_grid_setup(const float4 *__restrict__ partial,
                                                        int n_partial, float rn, float cs_req,
                                                        int max_cells, int n,
+                                                       const float *__restrict__ rn_dev,
                                                        GridMeta *__restrict__ meta)
 {
+    if (rn_dev) rn = *rn_dev;
     float4 b = make_float4(INFINITY, INFINITY, -INFINITY, -INFINITY);
     for (int k = threadIdx.x; k < n_partial; k += kBlock) {
         const float4 q = partial[k];
@@ -202,13 +204,20 @@ __global__ void k_fill_zero(uint4 *p, size_t n16)
 hipError_t launch_grid_build(const orca_agents_in &in, int n, const orca_params &p,
                              const Layout &L, const Work &w, hipStream_t stream)
 {
+    return launch_grid_build_rn(in, n, p.neighbor_dist, p.cell_size, nullptr, L, w, stream);
+}
+
+hipError_t launch_grid_build_rn(const orca_agents_in &in, int n, float rn, float cell_size,
+                                const float *rn_dev, const Layout &L, const Work &w,
+                                hipStream_t stream)
+{
     const int nb = (int)((n + kBlock - 1) / kBlock);
     const int nbb = nb < kBboxBlocks ? nb : kBboxBlocks;
     const int count_len = (int)L.max_cells;
     hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(kBlock), 0, stream, in.px, in.py, n,
                        w.partial, w.count, count_len);
-    hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(kBlock), 0, stream, w.partial, nbb,
-                       p.neighbor_dist, p.cell_size, count_len, n, w.meta);
+    hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(kBlock), 0, stream, w.partial, nbb, rn,
+                       cell_size, count_len, n, rn_dev, w.meta);
     hipLaunchKernelGGL(k_cell_count, dim3(nb), dim3(kBlock), 0, stream, in.px, in.py, n, w.meta,
                        w.cell, w.rank, w.count);
     return launch_scan_scatter(in, n, L, w, w.meta, stream);

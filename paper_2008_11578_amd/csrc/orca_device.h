@@ -104,21 +104,43 @@ __device__ __forceinline__ bool entry_less(uint64_t ea, uint64_t eb, const float
 #define ORCA_SCAN_UNROLL 8
 #endif
 constexpr int kScanUnroll = ORCA_SCAN_UNROLL;
+static_assert(kScanUnroll <= kScanPad, "candidate groups may read at most kScanPad past s0");
 
-// Visits the cell-order candidates [ra, rb) (ra < rb) in order, in groups of
-// kScanUnroll independent loads; the last group re-reads candidate rb - 1 for
-// its missing members and skips them, so there is no remainder loop.
+// Visits the cell-order candidates [ra, rb) (ra < rb) in groups of
+// kScanUnroll as visit(c, t, valid) (c = s0[t]).  A group always loads all its members
+// (the last one reads up to kScanUnroll - 1 entries past rb, inside s0 and
+// its padding) and passes valid = t < rb, so the visitor runs without a
+// remainder loop and can stay branch-free.  The next group is loaded before
+// the current one is visited.
 template <class F>
 __device__ __forceinline__ void scan_range(const float4 *__restrict__ s0, uint32_t ra, uint32_t rb,
                                            F &&visit)
 {
-    for (uint32_t t = ra; t < rb; t += kScanUnroll) {
-        float4 c[kScanUnroll];
+    // two register groups used in turn, so no group is copied; components a
+    // visitor does not read are never loaded
+    float4 c[kScanUnroll], d[kScanUnroll];
+    const float4 *p = s0 + ra;
 #pragma unroll
-        for (int q = 0; q < kScanUnroll; ++q) c[q] = s0[min(t + (uint32_t)q, rb - 1u)];
+    for (int q = 0; q < kScanUnroll; ++q) c[q] = p[q];
+    for (uint32_t t = ra;; t += 2 * kScanUnroll) {
+        const bool more1 = t + kScanUnroll < rb;
+        if (more1) {
 #pragma unroll
-        for (int q = 0; q < kScanUnroll; ++q)
-            if (t + (uint32_t)q < rb) visit(c[q], t + (uint32_t)q);
+            for (int q = 0; q < kScanUnroll; ++q) d[q] = p[kScanUnroll + q];
+        }
+#pragma unroll
+        for (int q = 0; q < kScanUnroll; ++q) visit(c[q], t + q, t + q < rb);
+        if (!more1) break;
+        const bool more2 = t + 2 * kScanUnroll < rb;
+        if (more2) {
+#pragma unroll
+            for (int q = 0; q < kScanUnroll; ++q) c[q] = p[2 * kScanUnroll + q];
+        }
+        const uint32_t u = t + kScanUnroll;
+#pragma unroll
+        for (int q = 0; q < kScanUnroll; ++q) visit(d[q], u + q, u + q < rb);
+        if (!more2) break;
+        p += 2 * kScanUnroll;
     }
 }
 
@@ -217,15 +239,16 @@ __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
     // keeps the index test out of this loop.
     uint64_t hlo = 0, hhi = 0;
     uint32_t total = 0;
-    scan_disc(g, start, s0, xd, yd, g.rn2, [&](const float4 &c, uint32_t) {
+    scan_disc(g, start, s0, xd, yd, g.rn2, [&](const float4 &c, uint32_t, bool valid) {
         const double key = nb_key(xi, yi, c.x, c.y);
-        if (key < g.rn2) {
-            const int bin = min((int)(key * bscale), kBins - 1);
-            const uint64_t inc = 1ull << ((bin & 7) * 8);
-            hlo += bin < 8 ? inc : 0ull;
-            hhi += bin < 8 ? 0ull : inc;
-            ++total;
-        }
+        const bool in = valid && key < g.rn2;
+        // equals min((int)(key * bscale), kBins - 1) for every key, and is
+        // defined also for the far (or invalid) candidates it is not used for
+        const int bin = (int)fmin(key * bscale, (double)(kBins - 1));
+        const int sh = (bin & 7) * 8;
+        hlo += (uint64_t)(in && bin < 8 ? 1u : 0u) << sh;
+        hhi += (uint64_t)(in && bin >= 8 ? 1u : 0u) << sh;
+        total += in ? 1u : 0u;
     });
     hlo -= 1ull;
     total -= 1u;
@@ -256,9 +279,9 @@ __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
         const double bnext = last ? INFINITY : (double)(bstar + 1);
         const double r2 = last ? g.rn2 : (double)(bstar + 1) * (g.rn2 / (double)kBins) * (1.0 + 1e-9);
         uint32_t slot = 0;
-        scan_disc(g, start, s0, xd, yd, r2, [&](const float4 &c, uint32_t t) {
+        scan_disc(g, start, s0, xd, yd, r2, [&](const float4 &c, uint32_t t, bool valid) {
             const double key = nb_key(xi, yi, c.x, c.y);
-            if (key < g.rn2 && key * bscale < bnext && __float_as_int(c.z) != self) {
+            if (valid && key < g.rn2 && key * bscale < bnext && __float_as_int(c.z) != self) {
                 if (slot < (uint32_t)kCap)  // always true: both passes count alike
                     buf[buf_idx<BLOCK>((int)slot, tid)] = pack_entry(key, t);
                 ++slot;
@@ -649,21 +672,36 @@ __device__ __forceinline__ void step_agent(int s, const GridMeta &g, const Scene
 #pragma unroll
     for (int q = 0; q < K; ++q) pos[q] = q < m ? (uint32_t)buf[buf_idx<BLOCK>(q, tid)] : 0u;
 
+    const float vmax = in.max_speed[i];
+    float prx = in.pref_x[i], pry = in.pref_y[i];
     const float fa = ci ? p.f10 : p.f00;  // f[ci][0]
     const float fb = ci ? p.f11 : p.f01;  // f[ci][1]
+    // neighbour states are loaded a group at a time without a branch (unused
+    // slots read position 0, a valid entry) so the loads of a group are in
+    // flight together; the half-planes of the group follow
+    constexpr int kHpGroup = 4;
 #pragma unroll
-    for (int q = 0; q < K; ++q) {
-        if (q < m) {
-            const float4 b0 = s0[pos[q]];
-            const float4 b1 = s1[pos[q]];
-            const float f = (__float_as_int(b1.z) & 1) ? fb : fa;
-            lines[q * BLOCK + tid] = halfplane(xi, yi, vxi, vyi, ri, b0.x, b0.y, b1.x, b1.y, b0.w,
-                                               f, p.inv_tau, p.inv_dt, i < __float_as_int(b0.z));
+    for (int q0 = 0; q0 < K; q0 += kHpGroup) {
+        float4 b0[kHpGroup], b1[kHpGroup];
+#pragma unroll
+        for (int u = 0; u < kHpGroup; ++u) {
+            if (q0 + u < K) {
+                b0[u] = s0[pos[q0 + u]];
+                b1[u] = s1[pos[q0 + u]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kHpGroup; ++u) {
+            const int q = q0 + u;
+            if (q < K && q < m) {
+                const float f = (__float_as_int(b1[u].z) & 1) ? fb : fa;
+                lines[q * BLOCK + tid] =
+                    halfplane(xi, yi, vxi, vyi, ri, b0[u].x, b0[u].y, b1[u].x, b1[u].y, b0[u].w,
+                              f, p.inv_tau, p.inv_dt, i < __float_as_int(b0[u].z));
+            }
         }
     }
 
-    const float vmax = in.max_speed[i];
-    float prx = in.pref_x[i], pry = in.pref_y[i];
     if (p.pref_is_goal) {
         const float gx = prx - xi, gy = pry - yi;
         const float d2 = gx * gx + gy * gy;

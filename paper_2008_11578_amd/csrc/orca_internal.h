@@ -13,6 +13,8 @@ constexpr int kWave = 64;
 constexpr int kBboxBlocks = 1024;   // partial bounding boxes per scene (max)
 constexpr int kScanTile = 2048;     // cells per scan tile (256 threads x 8)
 constexpr int kAlign = 256;
+constexpr int kScanPad = 16;        // float4 entries after the cell-ordered copy s0,
+                                    // so candidate groups may read past its end
 
 // Uniform grid of one scene, computed on the device from its bounding box.
 struct GridMeta {
@@ -171,6 +173,12 @@ Work bind(const Layout &L, void *ws);
 hipError_t launch_grid_build(const orca_agents_in &in, int n, const orca_params &p,
                              const Layout &L, const Work &w, hipStream_t stream);
 
+// The same with the neighbour distance read from device memory when rn_dev
+// is not null (a query radius computed on the device).
+hipError_t launch_grid_build_rn(const orca_agents_in &in, int n, float rn, float cell_size,
+                                const float *rn_dev, const Layout &L, const Work &w,
+                                hipStream_t stream);
+
 // Histogram scan and scatter into cell order; scan_meta supplies the number
 // of cells (n_cells) and of agents (n) of the whole cell space.
 hipError_t launch_scan_scatter(const orca_agents_in &in, int n, const Layout &L, const Work &w,
@@ -193,6 +201,18 @@ hipError_t launch_knn_export(const orca_agents_in &in, int n, const orca_params 
                              hipStream_t stream);
 
 hipError_t launch_fill_zero(void *ws, size_t bytes, hipStream_t stream);
+
+// Agent lifecycle (leaving at the goal, entering at clear spawn points).
+size_t lifecycle_extra_bytes(int64_t n, int64_t n_cand);
+hipError_t launch_remove_arrived(const orca_agents_in &in, const orca_agents_buf &out, int n,
+                                 int32_t *n_alive, int32_t *old_to_new, void *extra,
+                                 hipStream_t stream);
+size_t overlap_extra_bytes(int64_t n);
+hipError_t launch_overlap_stats(const orca_agents_in &in, int n, float reach, double *out,
+                                const Layout &L, const Work &w, void *extra, hipStream_t stream);
+hipError_t launch_spawn(const orca_agents_buf &state, int n, const orca_agents_in &cand,
+                        int n_cand, float t_clear, int32_t *n_total, uint8_t *accepted,
+                        const Layout &L, const Work &w, void *extra, hipStream_t stream);
 
 // Extra workspace of the adjoint: per-agent tau contributions and the edge
 // list (3 per agent) of contributions to neighbours with its transpose.

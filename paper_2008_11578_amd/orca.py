@@ -59,6 +59,11 @@ class CotangentsOut(ctypes.Structure):
     _fields_ = [(k, ctypes.c_void_p) for k in ("px", "py", "vx", "vy", "pref_x", "pref_y", "tau")]
 
 
+class AgentsBuf(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("px", "py", "vx", "vy", "pref_x", "pref_y",
+                                                "radius", "max_speed", "cls")]
+
+
 class StepEvents(ctypes.Structure):
     _fields_ = [("grid_begin", ctypes.c_void_p), ("step_begin", ctypes.c_void_p),
                 ("step_end", ctypes.c_void_p)]
@@ -100,6 +105,19 @@ def lib() -> ctypes.CDLL:
         L.orca_step_backward.argtypes = [ctypes.POINTER(AgentsIn), i32, ctypes.POINTER(OrcaParams),
                                          ctypes.POINTER(Cotangents), ctypes.POINTER(CotangentsOut),
                                          vp, sz, vp]
+        L.orca_lifecycle_workspace_bytes.restype = sz
+        L.orca_lifecycle_workspace_bytes.argtypes = [i32, i32]
+        L.orca_remove_arrived.restype = ctypes.c_int
+        L.orca_remove_arrived.argtypes = [ctypes.POINTER(AgentsIn), ctypes.POINTER(AgentsBuf), i32,
+                                          vp, vp, vp, sz, vp]
+        L.orca_spawn.restype = ctypes.c_int
+        L.orca_spawn.argtypes = [ctypes.POINTER(AgentsBuf), i32, i32, ctypes.POINTER(AgentsIn), i32,
+                                 ctypes.c_float, vp, vp, vp, sz, vp]
+        L.orca_overlap_workspace_bytes.restype = sz
+        L.orca_overlap_workspace_bytes.argtypes = [i32]
+        L.orca_overlap_stats.restype = ctypes.c_int
+        L.orca_overlap_stats.argtypes = [ctypes.POINTER(AgentsIn), i32, ctypes.c_float, vp, vp, sz,
+                                         vp]
         L.orca_status_string.restype = ctypes.c_char_p
         L.orca_status_string.argtypes = [ctypes.c_int]
         L.orca_version.restype = ctypes.c_char_p
@@ -332,4 +350,96 @@ def step_backward(state: State, params, ws: Workspace, g_px, g_py, g_vx, g_vy,
                                   ctypes.byref(c0), ws.ptr(), ws.nbytes, _stream_handle(stream))
     if rc != ORCA_OK:
         raise OrcaError("orca_step_backward", rc)
+    return out
+
+
+# ---- agent lifecycle -------------------------------------------------------
+
+SPAWN_MAX = 16384
+
+
+def _buf_of(state: State, n_min: int) -> AgentsBuf:
+    for k in STATE_FIELDS:
+        t = getattr(state, k)
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or not t.is_contiguous():
+            raise TypeError(f"{k} must be a contiguous device tensor")
+        if t.dtype != (torch.uint8 if k == "cls" else torch.float32) or t.numel() < n_min:
+            raise TypeError(f"{k} must hold at least {n_min} elements of the state's dtype")
+    return AgentsBuf(*[_ptr(getattr(state, k)) for k in STATE_FIELDS])
+
+
+class LifecycleWorkspace(Workspace):
+    """Workspace of remove_arrived / spawn for up to n agents and n_cand
+    spawn candidates."""
+
+    def __init__(self, n: int, n_cand: int = 0, device="cuda"):
+        self.nbytes = int(lib().orca_lifecycle_workspace_bytes(int(n), int(n_cand)))
+        self.n_max, self.cand_max = int(n), int(n_cand)
+        self.buf = torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device=device)
+        rc = lib().orca_workspace_init(_ptr(self.buf), self.nbytes, _stream_handle())
+        if rc != ORCA_OK:
+            raise OrcaError("orca_workspace_init", rc)
+
+
+def remove_arrived(state: State, out: State, ws: LifecycleWorkspace,
+                   old_to_new: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Writes the agents of `state` that have not reached their goal (pref is
+    read as the goal) to out[0:count], in order; returns count as a device
+    int32 tensor of one element.  `out` must not overlap `state`."""
+    n = state.n
+    ain = state.agents_in()
+    abuf = _buf_of(out, n)
+    if old_to_new is not None:
+        _check(old_to_new, "old_to_new", torch.int32, n)
+    count = torch.empty(1, dtype=torch.int32, device=state.px.device)
+    rc = lib().orca_remove_arrived(ctypes.byref(ain), ctypes.byref(abuf), n, _ptr(count),
+                                   _ptr(old_to_new), ws.ptr(), ws.nbytes, _stream_handle(stream))
+    if rc != ORCA_OK:
+        raise OrcaError("orca_remove_arrived", rc)
+    return count
+
+
+def spawn(state: State, n: int, cand: State, t_clear: float, ws: LifecycleWorkspace,
+          accepted: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Appends, in order, the candidates that keep clear of the first n agents
+    of `state` (capacity-sized buffers) and of the candidates accepted before
+    them for t_clear seconds; returns the new agent count as a device int32
+    tensor of one element."""
+    cap = state.n
+    nc = cand.n
+    abuf = _buf_of(state, n + nc)
+    cin = cand.agents_in()
+    if accepted is not None:
+        _check(accepted, "accepted", torch.uint8, nc)
+    total = torch.empty(1, dtype=torch.int32, device=state.px.device)
+    rc = lib().orca_spawn(ctypes.byref(abuf), int(n), int(cap), ctypes.byref(cin), nc,
+                          float(t_clear), _ptr(total), _ptr(accepted), ws.ptr(), ws.nbytes,
+                          _stream_handle(stream))
+    if rc != ORCA_OK:
+        raise OrcaError("orca_spawn", rc)
+    return total
+
+
+class OverlapWorkspace(Workspace):
+    """Workspace of overlap_stats for up to n agents."""
+
+    def __init__(self, n: int, device="cuda"):
+        self.nbytes = int(lib().orca_overlap_workspace_bytes(int(n)))
+        self.buf = torch.empty(max(self.nbytes, 256), dtype=torch.uint8, device=device)
+        rc = lib().orca_workspace_init(_ptr(self.buf), self.nbytes, _stream_handle())
+        if rc != ORCA_OK:
+            raise OrcaError("orca_workspace_init", rc)
+
+
+def overlap_stats(state: State, reach: float, ws: OverlapWorkspace, out=None,
+                  stream=None) -> torch.Tensor:
+    """(overlapping pairs, agents in an overlap, smallest clearance) over the
+    pairs closer than `reach`, as a device float64 tensor of 3."""
+    if out is None:
+        out = torch.empty(3, dtype=torch.float64, device=state.px.device)
+    ain = state.agents_in()
+    rc = lib().orca_overlap_stats(ctypes.byref(ain), state.n, float(reach), _ptr(out), ws.ptr(),
+                                  ws.nbytes, _stream_handle(stream))
+    if rc != ORCA_OK:
+        raise OrcaError("orca_overlap_stats", rc)
     return out

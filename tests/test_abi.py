@@ -139,3 +139,46 @@ def test_batched_argument_errors(orca_mod):
     assert call(max_neighbors=40) == -4
     assert call(mode=7) == -1
     assert call(ws_bytes=1024) == -2
+
+
+def test_lifecycle_argument_errors(orca_mod):
+    lib = orca_mod.lib()
+    ain = _in_fake(orca_mod)
+    buf = orca_mod.AgentsBuf(*([FAKE] * 9))
+    need = lib.orca_lifecycle_workspace_bytes(100, 50)
+    assert need > 0 and need % 256 == 0
+    assert lib.orca_lifecycle_workspace_bytes(-1, 0) == 0
+    assert lib.orca_lifecycle_workspace_bytes(100, 50) > lib.orca_lifecycle_workspace_bytes(100, 0)
+    # leaving: null count, null arrays, small workspace
+    assert lib.orca_remove_arrived(ctypes.byref(ain), ctypes.byref(buf), 100, None, None, FAKE,
+                                   need, None) == -1
+    bad_buf = orca_mod.AgentsBuf(*([FAKE] * 8 + [None]))
+    assert lib.orca_remove_arrived(ctypes.byref(ain), ctypes.byref(bad_buf), 100, FAKE, None,
+                                   FAKE, need, None) == -1
+    assert lib.orca_remove_arrived(ctypes.byref(ain), ctypes.byref(buf), -1, FAKE, None, FAKE,
+                                   need, None) == -1
+    assert lib.orca_remove_arrived(ctypes.byref(ain), ctypes.byref(buf), 100, FAKE, None, FAKE,
+                                   64, None) == -2
+
+    # entering: too many candidates, capacity short, negative window, small workspace
+    def spawn(n=100, cap=150, nc=50, t=1.0, ws_bytes=need, total=FAKE):
+        return lib.orca_spawn(ctypes.byref(buf), n, cap, ctypes.byref(ain), nc, t, total, None,
+                              FAKE, ws_bytes, None)
+
+    assert spawn(nc=orca_mod.SPAWN_MAX + 1, cap=1 << 30) == -1
+    assert spawn(cap=149) == -1
+    assert spawn(t=-1.0) == -1
+    assert spawn(t=float("inf")) == -1
+    assert spawn(total=None) == -1
+    assert spawn(ws_bytes=64) == -2
+
+
+def test_overlap_argument_errors(orca_mod):
+    lib = orca_mod.lib()
+    ain = _in_fake(orca_mod)
+    need = lib.orca_overlap_workspace_bytes(100)
+    assert need > 0 and lib.orca_overlap_workspace_bytes(-1) == 0
+    assert lib.orca_overlap_stats(ctypes.byref(ain), 100, 5.0, None, FAKE, need, None) == -1
+    assert lib.orca_overlap_stats(ctypes.byref(ain), 100, 0.0, FAKE, FAKE, need, None) == -1
+    assert lib.orca_overlap_stats(ctypes.byref(ain), -1, 5.0, FAKE, FAKE, need, None) == -1
+    assert lib.orca_overlap_stats(ctypes.byref(ain), 100, 5.0, FAKE, FAKE, 64, None) == -2
