@@ -178,7 +178,7 @@ __device__ __forceinline__ void adjoint_agent(int s, const AdjArgs &a, const Gri
 
     // -- forward recomputation (identical to dev::step_agent) --
     uint64_t *buf = reinterpret_cast<uint64_t *>(lines);
-    const int found = dev::knn_select<K, BLOCK>(g, a.start, a.s0, xi, yi, i, buf, tid);
+    const int found = dev::knn_select<K, BLOCK>(g, a.start, a.s0, xi, yi, i, buf, tid, g.rn2);
     const int kk = p.k < K ? p.k : K;
     const int m = found < kk ? found : kk;
     uint32_t pos[K];

@@ -152,7 +152,7 @@ __device__ __forceinline__ void batch_agent(const BatchArgs &a, int s, float4 *l
     const int sc = scene_of(a.off, a.S, s);
     const GridMeta g = a.meta[sc];
     const dev::SceneP p = dev::scene_params(a.prm[sc]);
-    dev::step_agent<K, BLOCK>(s, g, p, a.in, a.out, a.start, a.s0, a.s1, lines, tid);
+    dev::step_agent<K, BLOCK>(s, g, p, a.in, a.out, a.start, a.s0, a.s1, lines, tid, nullptr);
 }
 
 // Persistent step: wavefronts pop 64-agent tiles, first from their XCD's

@@ -44,6 +44,8 @@ Layout make_layout(int64_t n, int64_t n_scenes, int64_t max_cells)
     o = align_up(o + sizeof(float4) * (size_t)(n + kScanPad));
     L.s1 = o;
     o = align_up(o + sizeof(float4) * (size_t)n);
+    L.guess = o;
+    o = align_up(o + sizeof(float) * (size_t)n);
     L.total = o;
     return L;
 }
@@ -62,6 +64,7 @@ Work bind(const Layout &L, void *ws)
     w.tiles = (uint32_t *)(b + L.tiles);
     w.s0 = (float4 *)(b + L.s0);
     w.s1 = (float4 *)(b + L.s1);
+    w.guess = (float *)(b + L.guess);
     return w;
 }
 

@@ -225,33 +225,47 @@ __device__ __forceinline__ void scan_disc(const GridMeta &g, const uint32_t *__r
 }
 
 // Selects the (at most K) nearest agents of the lane into entries [0, m) of
-// its LDS buffer, ascending; returns m.
+// its LDS buffer, ascending; returns m.  rg2 (<= R_n^2) is a guess of a
+// squared radius that holds at least K candidates (from the previous step):
+// the counting pass first covers only that circle and falls back to the
+// whole neighbour circle when it holds fewer than K, so the result never
+// depends on the guess.
 template <int K, int BLOCK>
 __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
                           const float4 *__restrict__ s0, float xi, float yi, int self,
-                          uint64_t *buf, int tid)
+                          uint64_t *buf, int tid, double rg2)
 {
     constexpr int kCap = KnnShape<K>::kCap;
     const double xd = xi, yd = yi;
-    const double bscale = (double)kBins / g.rn2;
-    // pass 1: per-bin counts.  The lane's own agent is counted too (it is
-    // always scanned, with key 0, in bin 0) and taken out afterwards, which
-    // keeps the index test out of this loop.
-    uint64_t hlo = 0, hhi = 0;
-    uint32_t total = 0;
-    scan_disc(g, start, s0, xd, yd, g.rn2, [&](const float4 &c, uint32_t, bool valid) {
-        const double key = nb_key(xi, yi, c.x, c.y);
-        const bool in = valid && key < g.rn2;
-        // equals min((int)(key * bscale), kBins - 1) for every key, and is
-        // defined also for the far (or invalid) candidates it is not used for
-        const int bin = (int)fmin(key * bscale, (double)(kBins - 1));
-        const int sh = (bin & 7) * 8;
-        hlo += (uint64_t)(in && bin < 8 ? 1u : 0u) << sh;
-        hhi += (uint64_t)(in && bin >= 8 ? 1u : 0u) << sh;
-        total += in ? 1u : 0u;
-    });
-    hlo -= 1ull;
-    total -= 1u;
+    // pass 1: per-bin counts of the keys below r2c in kBins equal-area bins.
+    // The lane's own agent is counted too (it is always scanned, with key 0,
+    // in bin 0) and taken out afterwards, which keeps the index test out of
+    // this loop.
+    double r2c = rg2 < g.rn2 ? rg2 : g.rn2;
+    double bscale;
+    uint64_t hlo, hhi;
+    uint32_t total;
+    for (;;) {
+        bscale = (double)kBins / r2c;
+        hlo = 0;
+        hhi = 0;
+        total = 0;
+        scan_disc(g, start, s0, xd, yd, r2c, [&](const float4 &c, uint32_t, bool valid) {
+            const double key = nb_key(xi, yi, c.x, c.y);
+            const bool in = valid && key < r2c;
+            // equals min((int)(key * bscale), kBins - 1) for every key, and is
+            // defined also for the far (or invalid) candidates it is not used for
+            const int bin = (int)fmin(key * bscale, (double)(kBins - 1));
+            const int sh = (bin & 7) * 8;
+            hlo += (uint64_t)(in && bin < 8 ? 1u : 0u) << sh;
+            hhi += (uint64_t)(in && bin >= 8 ? 1u : 0u) << sh;
+            total += in ? 1u : 0u;
+        });
+        hlo -= 1ull;
+        total -= 1u;
+        if (total >= (uint32_t)K || !(r2c < g.rn2)) break;
+        r2c = g.rn2;  // the guessed circle holds fewer than K: count them all
+    }
 
     // threshold bin b*: the first bin at which the cumulative count reaches K
     uint32_t cum = 0, take = 0;
@@ -277,11 +291,11 @@ __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
         // far above the rounding of key * bscale).
         const bool last = bstar + 1 >= kBins;
         const double bnext = last ? INFINITY : (double)(bstar + 1);
-        const double r2 = last ? g.rn2 : (double)(bstar + 1) * (g.rn2 / (double)kBins) * (1.0 + 1e-9);
+        const double r2 = last ? r2c : (double)(bstar + 1) * (r2c / (double)kBins) * (1.0 + 1e-9);
         uint32_t slot = 0;
         scan_disc(g, start, s0, xd, yd, r2, [&](const float4 &c, uint32_t t, bool valid) {
             const double key = nb_key(xi, yi, c.x, c.y);
-            if (valid && key < g.rn2 && key * bscale < bnext && __float_as_int(c.z) != self) {
+            if (valid && key < r2c && key * bscale < bnext && __float_as_int(c.z) != self) {
                 if (slot < (uint32_t)kCap)  // always true: both passes count alike
                     buf[buf_idx<BLOCK>((int)slot, tid)] = pack_entry(key, t);
                 ++slot;
@@ -651,28 +665,46 @@ __device__ __host__ __forceinline__ SceneP scene_params(const orca_params &p)
 // One whole ORCA step of the agent at cell-order position s: neighbours,
 // half-planes (into the lane's LDS column), LP2, LP3 if needed, update.
 // `lines` is a [max(K, 8)][BLOCK] float4 array; lane `tid` owns column tid.
+// `guess` (caller order, nullable) keeps each agent's K-th neighbour
+// distance between steps (0: none); it only narrows the counting pass.
 template <int K, int BLOCK>
 __device__ __forceinline__ void step_agent(int s, const GridMeta &g, const SceneP &p,
                                            const orca_agents_in &in, const orca_agents_out &out,
                                            const uint32_t *__restrict__ start,
                                            const float4 *__restrict__ s0,
-                                           const float4 *__restrict__ s1, float4 *lines, int tid)
+                                           const float4 *__restrict__ s1, float4 *lines, int tid,
+                                           float *__restrict__ guess)
 {
     const float4 me0 = s0[s];
     const float4 me1 = s1[s];
     const int i = __float_as_int(me0.z);
     const float xi = me0.x, yi = me0.y, ri = me0.w, vxi = me1.x, vyi = me1.y;
     const int ci = __float_as_int(me1.z) & 1;
+    const float vmax = in.max_speed[i];
+
+    // the K nearest of the previous step, moved apart by at most their two
+    // speeds times dt, stay within d_K + 2 v dt; a small slack covers the
+    // faster neighbours the lane does not know of
+    double rg2 = g.rn2;
+    if (guess) {
+        const float d = guess[i];
+        if (d > 0.0f) {
+            const double r = (double)d + 2.0 * (double)p.dt * (double)vmax + 0.05 * (double)g.rn;
+            rg2 = fmin(r * r, g.rn2);
+        }
+    }
 
     uint64_t *buf = reinterpret_cast<uint64_t *>(lines);
-    const int found = knn_select<K, BLOCK>(g, start, s0, xi, yi, i, buf, tid);
+    const int found = knn_select<K, BLOCK>(g, start, s0, xi, yi, i, buf, tid, rg2);
+    if (guess)
+        guess[i] = found == K ? sqrtf(__uint_as_float((uint32_t)(buf[buf_idx<BLOCK>(K - 1, tid)] >> 32)))
+                              : 0.0f;
     const int kk = p.k < K ? p.k : K;
     const int m = found < kk ? found : kk;
     uint32_t pos[K];
 #pragma unroll
     for (int q = 0; q < K; ++q) pos[q] = q < m ? (uint32_t)buf[buf_idx<BLOCK>(q, tid)] : 0u;
 
-    const float vmax = in.max_speed[i];
     float prx = in.pref_x[i], pry = in.pref_y[i];
     const float fa = ci ? p.f10 : p.f00;  // f[ci][0]
     const float fb = ci ? p.f11 : p.f01;  // f[ci][1]

@@ -35,7 +35,7 @@ struct GridMeta {
 
 // Byte offsets of the workspace regions (all 256-byte aligned).
 struct Layout {
-    size_t meta, partial, queue, cell, rank, count, start, tiles, s0, s1, total;
+    size_t meta, partial, queue, cell, rank, count, start, tiles, s0, s1, guess, total;
     int64_t n, n_scenes, max_cells, n_tiles;
 };
 
@@ -164,6 +164,7 @@ struct Work {
     uint32_t *tiles;
     float4 *s0;   // cell order: (px, py, bits(caller index), radius)
     float4 *s1;   // cell order: (vx, vy, bits(class), 0)
+    float *guess; // caller order: K-th neighbour distance of the last step (0: none)
 };
 
 Work bind(const Layout &L, void *ws);

@@ -20,6 +20,7 @@ struct StepArgs {
     int k;
     int32_t *nbr;   // knn export only
     int32_t *cnt;
+    float *guess;   // per-agent K-th neighbour distance kept between steps
     orca_params prm;
 };
 
@@ -35,7 +36,7 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, dev::SceneP p)
     const int s = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + tid;
     if (s >= a.n) return;
     const GridMeta g = *a.meta;
-    dev::step_agent<K, BLOCK>(s, g, p, a.in, a.out, a.start, a.s0, a.s1, lines, tid);
+    dev::step_agent<K, BLOCK>(s, g, p, a.in, a.out, a.start, a.s0, a.s1, lines, tid, a.guess);
 }
 
 template <int K, int BLOCK>
@@ -49,7 +50,7 @@ __global__ __launch_bounds__(BLOCK) void k_knn_export(StepArgs a)
     const float4 me0 = a.s0[s];
     const int i = __float_as_int(me0.z);
     uint64_t *buf = reinterpret_cast<uint64_t *>(lds);
-    const int found = knn_select<K, BLOCK>(g, a.start, a.s0, me0.x, me0.y, i, buf, tid);
+    const int found = knn_select<K, BLOCK>(g, a.start, a.s0, me0.x, me0.y, i, buf, tid, g.rn2);
     const int m = found < a.k ? found : a.k;
     if (a.nbr) {
         int32_t *row = a.nbr + (int64_t)i * a.k;
@@ -76,6 +77,7 @@ StepArgs make_args(const orca_agents_in &in, const orca_agents_out *out, int n,
     a.k = p.max_neighbors;
     a.nbr = nullptr;
     a.cnt = nullptr;
+    a.guess = w.guess;
     a.prm = p;
     return a;
 }

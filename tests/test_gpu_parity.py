@@ -142,6 +142,30 @@ def test_step_deterministic_and_inplace():
         assert torch.equal(getattr(a, k), getattr(c, k)), k
 
 
+def test_step_independent_of_kept_neighbour_distances():
+    """The workspace keeps each agent's K-th neighbour distance to narrow the
+    next counting pass.  Stale values (a denser crowd, a sparser crowd, a
+    different state of the same crowd) must change nothing: every output is
+    bit-identical to a step on a fresh workspace."""
+    import torch
+    from paper_2008_11578_amd import orca
+    sc = scenarios.random_state(30000, 100.0, seed=5, n_vehicles=300)
+    st = orca.State.from_arrays(sc)
+    fresh = orca.step(st, sc.params, orca.Workspace(st.n))
+    for side in (40.0, 400.0, 100.0):  # too small, too large, similar distances
+        other = scenarios.random_state(30000, side, seed=6, n_vehicles=300)
+        ws = orca.Workspace(st.n)
+        o = orca.State.from_arrays(other)
+        for _ in range(2):
+            orca.step(o, other.params, ws, out=o)
+        got = orca.step(st, sc.params, ws)
+        got2 = orca.step(st, sc.params, ws)  # now with its own distances
+        torch.cuda.synchronize()
+        for k in ("px", "py", "vx", "vy"):
+            assert torch.equal(getattr(fresh, k), getattr(got, k)), (side, k)
+            assert torch.equal(getattr(fresh, k), getattr(got2, k)), (side, k)
+
+
 def test_step_edge_cases():
     p = scenarios.Params(dt=0.1, neighbor_dist=5.0, max_neighbors=10, pref_is_goal=0)
     # single agent: desired velocity clipped to the cap
