@@ -185,30 +185,19 @@ __device__ __forceinline__ void adjoint_agent(int s, const AdjArgs &a, const Gri
 #pragma unroll
     for (int q = 0; q < K; ++q)
         pos[q] = q < m ? (uint32_t)buf[dev::buf_idx<BLOCK>(q, tid)] : 0u;
-    const float fa = ci ? p.f10 : p.f00;
-    const float fb = ci ? p.f11 : p.f01;
-#pragma unroll
-    for (int q = 0; q < K; ++q) {
-        if (q < m) {
-            const float4 b0 = a.s0[pos[q]];
-            const float4 b1 = a.s1[pos[q]];
-            const float f = (__float_as_int(b1.z) & 1) ? fb : fa;
-            lines[q * BLOCK + tid] = dev::halfplane(xi, yi, vxi, vyi, ri, b0.x, b0.y, b1.x, b1.y,
-                                                    b0.w, f, p.inv_tau, p.inv_dt,
-                                                    i < __float_as_int(b0.z));
-        }
-    }
+    dev::build_halfplanes<K, BLOCK>(pos, m, a.s0, a.s1, xi, yi, vxi, vyi, ri, i, ci, p, lines,
+                                    tid);
     const float vmax = a.in.max_speed[i];
     const float pin_x = a.in.pref_x[i], pin_y = a.in.pref_y[i];
     float prx = pin_x, pry = pin_y;
+    dev::desired_velocity(p, xi, yi, vmax, prx, pry);
+    // the goal-mode quantities the desired velocity was formed from
     float gxg = 0.0f, gyg = 0.0f, d2g = 0.0f, scg = 0.0f;
     if (p.pref_is_goal) {
         gxg = pin_x - xi;
         gyg = pin_y - yi;
         d2g = gxg * gxg + gyg * gyg;
         scg = d2g > 0.0f ? fminf(vmax / sqrtf(d2g), p.inv_dt) : 0.0f;
-        prx = gxg * scg;
-        pry = gyg * scg;
     }
     dev::LdsLines<BLOCK> src{lines, tid};
     float vx, vy;
@@ -316,6 +305,8 @@ __device__ __forceinline__ void adjoint_agent(int s, const AdjArgs &a, const Gri
     }
 
     // -- ORCA half-planes of the involved lines --
+    const float fa = ci ? p.f10 : p.f00;  // f[ci][0]
+    const float fb = ci ? p.f11 : p.f01;  // f[ci][1]
     float spx = 0.0f, spy = 0.0f, svx = 0.0f, svy = 0.0f, taub = 0.0f;
 #pragma unroll
     for (int e = 0; e < kEdges; ++e) {

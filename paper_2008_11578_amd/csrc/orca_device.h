@@ -32,6 +32,7 @@ __device__ __forceinline__ float det2(float ax, float ay, float bx, float by)
     return ax * by - ay * bx;
 }
 
+
 // Squared distance in double from FP32 positions, each operation rounded
 // separately (no fused multiply-add): the neighbour order is defined on it.
 __device__ __forceinline__ double nb_key(float xi, float yi, float xj, float yj)
@@ -662,6 +663,57 @@ __device__ __host__ __forceinline__ SceneP scene_params(const orca_params &p)
     return s;
 }
 
+// The half-planes of the agent's m neighbours into its LDS column.
+// Neighbour states are loaded a group at a time without a branch (unused
+// slots read position 0, a valid entry) so the loads of a group are in
+// flight together; the half-planes of the group follow.
+template <int K, int BLOCK>
+__device__ __forceinline__ void build_halfplanes(const uint32_t (&pos)[K], int m,
+                                                 const float4 *__restrict__ s0,
+                                                 const float4 *__restrict__ s1, float xi,
+                                                 float yi, float vxi, float vyi, float ri, int i,
+                                                 int ci, const SceneP &p, float4 *lines, int tid)
+{
+    const float fa = ci ? p.f10 : p.f00;  // f[ci][0]
+    const float fb = ci ? p.f11 : p.f01;  // f[ci][1]
+    constexpr int kHpGroup = 4;
+#pragma unroll
+    for (int q0 = 0; q0 < K; q0 += kHpGroup) {
+        float4 b0[kHpGroup], b1[kHpGroup];
+#pragma unroll
+        for (int u = 0; u < kHpGroup; ++u) {
+            if (q0 + u < K) {
+                b0[u] = s0[pos[q0 + u]];
+                b1[u] = s1[pos[q0 + u]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kHpGroup; ++u) {
+            const int q = q0 + u;
+            if (q < K && q < m) {
+                const float f = (__float_as_int(b1[u].z) & 1) ? fb : fa;
+                lines[q * BLOCK + tid] =
+                    halfplane(xi, yi, vxi, vyi, ri, b0[u].x, b0[u].y, b1[u].x, b1[u].y, b0[u].w,
+                              f, p.inv_tau, p.inv_dt, i < __float_as_int(b0[u].z));
+            }
+        }
+    }
+}
+
+// Goal mode: the pref input (the goal) becomes the desired velocity
+// (g - p) min(v_max / |g - p|, 1/dt), zero at the goal.
+__device__ __forceinline__ void desired_velocity(const SceneP &p, float xi, float yi, float vmax,
+                                                 float &prx, float &pry)
+{
+    if (p.pref_is_goal) {
+        const float gx = prx - xi, gy = pry - yi;
+        const float d2 = gx * gx + gy * gy;
+        const float sc = d2 > 0.0f ? fminf(vmax / sqrtf(d2), p.inv_dt) : 0.0f;
+        prx = gx * sc;
+        pry = gy * sc;
+    }
+}
+
 // One whole ORCA step of the agent at cell-order position s: neighbours,
 // half-planes (into the lane's LDS column), LP2, LP3 if needed, update.
 // `lines` is a [max(K, 8)][BLOCK] float4 array; lane `tid` owns column tid.
@@ -706,41 +758,8 @@ __device__ __forceinline__ void step_agent(int s, const GridMeta &g, const Scene
     for (int q = 0; q < K; ++q) pos[q] = q < m ? (uint32_t)buf[buf_idx<BLOCK>(q, tid)] : 0u;
 
     float prx = in.pref_x[i], pry = in.pref_y[i];
-    const float fa = ci ? p.f10 : p.f00;  // f[ci][0]
-    const float fb = ci ? p.f11 : p.f01;  // f[ci][1]
-    // neighbour states are loaded a group at a time without a branch (unused
-    // slots read position 0, a valid entry) so the loads of a group are in
-    // flight together; the half-planes of the group follow
-    constexpr int kHpGroup = 4;
-#pragma unroll
-    for (int q0 = 0; q0 < K; q0 += kHpGroup) {
-        float4 b0[kHpGroup], b1[kHpGroup];
-#pragma unroll
-        for (int u = 0; u < kHpGroup; ++u) {
-            if (q0 + u < K) {
-                b0[u] = s0[pos[q0 + u]];
-                b1[u] = s1[pos[q0 + u]];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kHpGroup; ++u) {
-            const int q = q0 + u;
-            if (q < K && q < m) {
-                const float f = (__float_as_int(b1[u].z) & 1) ? fb : fa;
-                lines[q * BLOCK + tid] =
-                    halfplane(xi, yi, vxi, vyi, ri, b0[u].x, b0[u].y, b1[u].x, b1[u].y, b0[u].w,
-                              f, p.inv_tau, p.inv_dt, i < __float_as_int(b0[u].z));
-            }
-        }
-    }
-
-    if (p.pref_is_goal) {
-        const float gx = prx - xi, gy = pry - yi;
-        const float d2 = gx * gx + gy * gy;
-        const float sc = d2 > 0.0f ? fminf(vmax / sqrtf(d2), p.inv_dt) : 0.0f;
-        prx = gx * sc;
-        pry = gy * sc;
-    }
+    build_halfplanes<K, BLOCK>(pos, m, s0, s1, xi, yi, vxi, vyi, ri, i, ci, p, lines, tid);
+    desired_velocity(p, xi, yi, vmax, prx, pry);
 
     LdsLines<BLOCK> src{lines, tid};
     float vx, vy;
