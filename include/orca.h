@@ -52,6 +52,7 @@ extern "C" {
 #define ORCA_ERANGE (-4)     /* max_neighbors outside 1..ORCA_K_MAX */
 
 #define ORCA_K_MAX 32
+#define ORCA_N_MAX 268435456  /* agents per call (2^28) of the neighbour search */
 
 /* Per-agent inputs (device pointers, length n, caller order).
  * pref_x/pref_y hold the goal position when orca_params.pref_is_goal is 1

@@ -178,13 +178,14 @@ __device__ __forceinline__ void adjoint_agent(int s, const AdjArgs &a, const Gri
 
     // -- forward recomputation (identical to dev::step_agent) --
     uint64_t *buf = reinterpret_cast<uint64_t *>(lines);
-    const int found = dev::knn_select<K, BLOCK>(g, a.start, a.s0, xi, yi, i, buf, tid, g.rn2);
+    const int found = dev::knn_select<K, BLOCK>(g, a.start, a.s0, xi, yi, i, (uint32_t)s, buf, tid,
+                                                g.rn2);
     const int kk = p.k < K ? p.k : K;
     const int m = found < kk ? found : kk;
     uint32_t pos[K];
 #pragma unroll
     for (int q = 0; q < K; ++q)
-        pos[q] = q < m ? (uint32_t)buf[dev::buf_idx<BLOCK>(q, tid)] : 0u;
+        pos[q] = q < m ? dev::entry_pos(buf[dev::buf_idx<BLOCK>(q, tid)]) : 0u;
     dev::build_halfplanes<K, BLOCK>(pos, m, a.s0, a.s1, xi, yi, vxi, vyi, ri, i, ci, p, lines,
                                     tid);
     const float vmax = a.in.max_speed[i];

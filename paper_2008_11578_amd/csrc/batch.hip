@@ -144,6 +144,7 @@ struct BatchArgs {
     const float4 *s0;
     const float4 *s1;
     uint32_t *queue;
+    float *guess;  // per-agent K-th neighbour distance kept between steps
 };
 
 template <int K, int BLOCK>
@@ -152,7 +153,7 @@ __device__ __forceinline__ void batch_agent(const BatchArgs &a, int s, float4 *l
     const int sc = scene_of(a.off, a.S, s);
     const GridMeta g = a.meta[sc];
     const dev::SceneP p = dev::scene_params(a.prm[sc]);
-    dev::step_agent<K, BLOCK>(s, g, p, a.in, a.out, a.start, a.s0, a.s1, lines, tid, nullptr);
+    dev::step_agent<K, BLOCK>(s, g, p, a.in, a.out, a.start, a.s0, a.s1, lines, tid, a.guess);
 }
 
 // Persistent step: wavefronts pop 64-agent tiles, first from their XCD's
@@ -254,6 +255,7 @@ hipError_t launch_batched(const orca_agents_in &in, const orca_agents_out &out, 
     a.s0 = w.s0;
     a.s1 = w.s1;
     a.queue = w.queue;
+    a.guess = w.guess;
     if (k_max <= 4) return launch_step_batched_k<4>(a, mode, stream);
     if (k_max <= 8) return launch_step_batched_k<8>(a, mode, stream);
     if (k_max <= 10) return launch_step_batched_k<10>(a, mode, stream);

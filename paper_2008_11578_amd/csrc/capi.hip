@@ -167,7 +167,7 @@ constexpr int64_t kMaxCellsCap = (int64_t)1 << 30;
 
 int prepare(int32_t n, const orca_params *params, void *ws, size_t ws_bytes, Layout &L)
 {
-    if (n < 0) return ORCA_EINVAL;
+    if (n < 0 || n > ORCA_N_MAX) return ORCA_EINVAL;
     const int rc = check_params(params);
     if (rc != ORCA_OK) return rc;
     if (n == 0) return ORCA_OK;
@@ -249,7 +249,7 @@ int orca_step(const orca_agents_in *in, const orca_agents_out *out, int32_t n,
 int orca_step_batched(const orca_agents_in *in, const orca_agents_out *out, int32_t n,
                       const orca_batch *batch, void *ws, size_t ws_bytes, hipStream_t stream)
 {
-    if (n < 0 || !batch) return ORCA_EINVAL;
+    if (n < 0 || n > ORCA_N_MAX || !batch) return ORCA_EINVAL;
     if (batch->n_scenes < 1 || !batch->scene_off || !batch->params) return ORCA_EINVAL;
     if (batch->max_neighbors < 1 || batch->max_neighbors > ORCA_K_MAX) return ORCA_ERANGE;
     if (batch->mode != 0 && batch->mode != 1) return ORCA_EINVAL;
@@ -280,7 +280,7 @@ int orca_step_backward(const orca_agents_in *in, int32_t n, const orca_params *p
                        const orca_cotangents *g1, const orca_cotangents_out *g0, void *ws,
                        size_t ws_bytes, hipStream_t stream)
 {
-    if (n < 0) return ORCA_EINVAL;
+    if (n < 0 || n > ORCA_N_MAX) return ORCA_EINVAL;
     int rc = check_params(params);
     if (rc != ORCA_OK) return rc;
     if (n == 0) return ORCA_OK;

@@ -81,10 +81,19 @@ __device__ __forceinline__ int buf_idx(int e, int tid)
     return (e >> 1) * (2 * BLOCK) + 2 * tid + (e & 1);
 }
 
-__device__ __forceinline__ uint64_t pack_entry(double key, uint32_t t)
+// Entry = (float(key) bits << 32) | (bin << 28) | cell-order position; the
+// position needs 28 bits (at most 2^28 agents), the bin field is only read
+// by the single-pass selection below.
+constexpr uint32_t kPosBits = 28;
+constexpr uint32_t kPosMask = (1u << kPosBits) - 1u;
+
+__device__ __forceinline__ uint64_t pack_entry(double key, uint32_t t, uint32_t bin = 0u)
 {
-    return ((uint64_t)__float_as_uint((float)key) << 32) | (uint64_t)t;
+    return ((uint64_t)__float_as_uint((float)key) << 32) | (uint64_t)((bin << kPosBits) | t);
 }
+
+__device__ __forceinline__ uint32_t entry_pos(uint64_t e) { return (uint32_t)e & kPosMask; }
+__device__ __forceinline__ uint32_t entry_bin(uint64_t e) { return (uint32_t)e >> kPosBits; }
 
 // Strict (key, caller index) order of two buffer entries.
 __device__ __forceinline__ bool entry_less(uint64_t ea, uint64_t eb, const float4 *__restrict__ s0,
@@ -92,8 +101,8 @@ __device__ __forceinline__ bool entry_less(uint64_t ea, uint64_t eb, const float
 {
     const uint32_t ha = (uint32_t)(ea >> 32), hb = (uint32_t)(eb >> 32);
     if (ha != hb) return ha < hb;
-    const float4 ca = s0[(uint32_t)ea];
-    const float4 cb = s0[(uint32_t)eb];
+    const float4 ca = s0[entry_pos(ea)];
+    const float4 cb = s0[entry_pos(eb)];
     const double ka = nb_key(xi, yi, ca.x, ca.y);
     const double kb = nb_key(xi, yi, cb.x, cb.y);
     if (ka != kb) return ka < kb;
@@ -234,14 +243,15 @@ __device__ __forceinline__ void scan_disc(const GridMeta &g, const uint32_t *__r
 template <int K, int BLOCK>
 __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
                           const float4 *__restrict__ s0, float xi, float yi, int self,
-                          uint64_t *buf, int tid, double rg2)
+                          uint32_t spos, uint64_t *buf, int tid, double rg2)
 {
     constexpr int kCap = KnnShape<K>::kCap;
     const double xd = xi, yd = yi;
-    // pass 1: per-bin counts of the keys below r2c in kBins equal-area bins.
-    // The lane's own agent is counted too (it is always scanned, with key 0,
-    // in bin 0) and taken out afterwards, which keeps the index test out of
-    // this loop.
+    // pass 1: per-bin counts of the keys below r2c in kBins equal-area bins,
+    // and the candidates themselves while they fit the buffer.  The lane's
+    // own agent is counted (and stored) too -- it is always scanned, with
+    // key 0, in bin 0 -- and taken out afterwards, which keeps the index
+    // test out of this loop.
     double r2c = rg2 < g.rn2 ? rg2 : g.rn2;
     double bscale;
     uint64_t hlo, hhi;
@@ -251,7 +261,7 @@ __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
         hlo = 0;
         hhi = 0;
         total = 0;
-        scan_disc(g, start, s0, xd, yd, r2c, [&](const float4 &c, uint32_t, bool valid) {
+        scan_disc(g, start, s0, xd, yd, r2c, [&](const float4 &c, uint32_t t, bool valid) {
             const double key = nb_key(xi, yi, c.x, c.y);
             const bool in = valid && key < r2c;
             // equals min((int)(key * bscale), kBins - 1) for every key, and is
@@ -260,6 +270,8 @@ __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
             const int sh = (bin & 7) * 8;
             hlo += (uint64_t)(in && bin < 8 ? 1u : 0u) << sh;
             hhi += (uint64_t)(in && bin >= 8 ? 1u : 0u) << sh;
+            if (in && total < (uint32_t)kCap)
+                buf[buf_idx<BLOCK>((int)total, tid)] = pack_entry(key, t, (uint32_t)bin);
             total += in ? 1u : 0u;
         });
         hlo -= 1ull;
@@ -267,6 +279,8 @@ __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
         if (total >= (uint32_t)K || !(r2c < g.rn2)) break;
         r2c = g.rn2;  // the guessed circle holds fewer than K: count them all
     }
+    // every candidate of the circle (and the lane's own entry) is in the buffer
+    const bool captured = total + 1u <= (uint32_t)kCap;
 
     // threshold bin b*: the first bin at which the cumulative count reaches K
     uint32_t cum = 0, take = 0;
@@ -284,24 +298,37 @@ __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
     if (!found) take = total;
 
     if (total <= 255u && take <= (uint32_t)kCap) {
-        // pass 2: collect the candidates of bins <= b*, in scan order.  For
-        // b* below the last bin, bin <= b* is exactly key * bscale < b* + 1
-        // (truncation of a non-negative value), so both passes count alike.
-        // Every such key is below (b* + 1) R_n^2 / kBins, so only rows and
-        // chords of that smaller circle are visited (with a relative margin
-        // far above the rounding of key * bscale).
-        const bool last = bstar + 1 >= kBins;
-        const double bnext = last ? INFINITY : (double)(bstar + 1);
-        const double r2 = last ? r2c : (double)(bstar + 1) * (r2c / (double)kBins) * (1.0 + 1e-9);
-        uint32_t slot = 0;
-        scan_disc(g, start, s0, xd, yd, r2, [&](const float4 &c, uint32_t t, bool valid) {
-            const double key = nb_key(xi, yi, c.x, c.y);
-            if (valid && key < r2c && key * bscale < bnext && __float_as_int(c.z) != self) {
-                if (slot < (uint32_t)kCap)  // always true: both passes count alike
-                    buf[buf_idx<BLOCK>((int)slot, tid)] = pack_entry(key, t);
-                ++slot;
+        if (captured) {
+            // the candidates of bins <= b* are already in the buffer: keep
+            // them in place, dropping the lane's own entry
+            uint32_t w = 0;
+            for (uint32_t e = 0; e <= total; ++e) {
+                const uint64_t ent = buf[buf_idx<BLOCK>((int)e, tid)];
+                if (entry_pos(ent) != spos && (int)entry_bin(ent) <= bstar) {
+                    buf[buf_idx<BLOCK>((int)w, tid)] = ent;
+                    ++w;
+                }
             }
-        });
+        } else {
+            // pass 2: collect the candidates of bins <= b*, in scan order.  For
+            // b* below the last bin, bin <= b* is exactly key * bscale < b* + 1
+            // (truncation of a non-negative value), so both passes count alike.
+            // Every such key is below (b* + 1) R_n^2 / kBins, so only rows and
+            // chords of that smaller circle are visited (with a relative margin
+            // far above the rounding of key * bscale).
+            const bool last = bstar + 1 >= kBins;
+            const double bnext = last ? INFINITY : (double)(bstar + 1);
+            const double r2 = last ? r2c : (double)(bstar + 1) * (r2c / (double)kBins) * (1.0 + 1e-9);
+            uint32_t slot = 0;
+            scan_disc(g, start, s0, xd, yd, r2, [&](const float4 &c, uint32_t t, bool valid) {
+                const double key = nb_key(xi, yi, c.x, c.y);
+                if (valid && key < r2c && key * bscale < bnext && __float_as_int(c.z) != self) {
+                    if (slot < (uint32_t)kCap)  // always true: both passes count alike
+                        buf[buf_idx<BLOCK>((int)slot, tid)] = pack_entry(key, t);
+                    ++slot;
+                }
+            });
+        }
         // order: a sorting network in registers when the entries fit it,
         // which orders them by (FP32 key, cell-order position); an FP32-key
         // tie among the entries that decide the result needs the (FP64 key,
@@ -747,7 +774,7 @@ __device__ __forceinline__ void step_agent(int s, const GridMeta &g, const Scene
     }
 
     uint64_t *buf = reinterpret_cast<uint64_t *>(lines);
-    const int found = knn_select<K, BLOCK>(g, start, s0, xi, yi, i, buf, tid, rg2);
+    const int found = knn_select<K, BLOCK>(g, start, s0, xi, yi, i, (uint32_t)s, buf, tid, rg2);
     if (guess)
         guess[i] = found == K ? sqrtf(__uint_as_float((uint32_t)(buf[buf_idx<BLOCK>(K - 1, tid)] >> 32)))
                               : 0.0f;
@@ -755,7 +782,7 @@ __device__ __forceinline__ void step_agent(int s, const GridMeta &g, const Scene
     const int m = found < kk ? found : kk;
     uint32_t pos[K];
 #pragma unroll
-    for (int q = 0; q < K; ++q) pos[q] = q < m ? (uint32_t)buf[buf_idx<BLOCK>(q, tid)] : 0u;
+    for (int q = 0; q < K; ++q) pos[q] = q < m ? entry_pos(buf[buf_idx<BLOCK>(q, tid)]) : 0u;
 
     float prx = in.pref_x[i], pry = in.pref_y[i];
     build_halfplanes<K, BLOCK>(pos, m, s0, s1, xi, yi, vxi, vyi, ri, i, ci, p, lines, tid);

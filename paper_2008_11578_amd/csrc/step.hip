@@ -50,12 +50,13 @@ __global__ __launch_bounds__(BLOCK) void k_knn_export(StepArgs a)
     const float4 me0 = a.s0[s];
     const int i = __float_as_int(me0.z);
     uint64_t *buf = reinterpret_cast<uint64_t *>(lds);
-    const int found = knn_select<K, BLOCK>(g, a.start, a.s0, me0.x, me0.y, i, buf, tid, g.rn2);
+    const int found =
+        knn_select<K, BLOCK>(g, a.start, a.s0, me0.x, me0.y, i, (uint32_t)s, buf, tid, g.rn2);
     const int m = found < a.k ? found : a.k;
     if (a.nbr) {
         int32_t *row = a.nbr + (int64_t)i * a.k;
         for (int q = 0; q < a.k; ++q)
-            row[q] = q < m ? __float_as_int(a.s0[(uint32_t)buf[buf_idx<BLOCK>(q, tid)]].z) : -1;
+            row[q] = q < m ? __float_as_int(a.s0[dev::entry_pos(buf[buf_idx<BLOCK>(q, tid)])].z) : -1;
     }
     if (a.cnt) a.cnt[i] = m;
 }

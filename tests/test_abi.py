@@ -113,6 +113,9 @@ def test_step_argument_errors(orca_mod):
     # workspace too small
     assert lib.orca_step(ctypes.byref(ain), ctypes.byref(aout), 10, ctypes.byref(p), FAKE, 64,
                          None) == -2
+    # beyond the 2^28 agents the neighbour search addresses
+    assert lib.orca_step(ctypes.byref(ain), ctypes.byref(aout), (1 << 28) + 1, ctypes.byref(p),
+                         FAKE, 1 << 62, None) == -1
     assert lib.orca_build_grid(ctypes.byref(ain), 10, ctypes.byref(p), FAKE, 64, None, None,
                                None) == -2
 
