@@ -768,7 +768,7 @@ __device__ __forceinline__ void step_agent(int s, const GridMeta &g, const Scene
     if (guess) {
         const float d = guess[i];
         if (d > 0.0f) {
-            const double r = (double)d + 2.0 * (double)p.dt * (double)vmax + 0.05 * (double)g.rn;
+            const double r = (double)d + 2.0 * (double)p.dt * (double)vmax + 0.005 * (double)g.rn;
             rg2 = fmin(r * r, g.rn2);
         }
     }
