@@ -320,9 +320,10 @@ def main(argv=None):
                     help="oracle steps in the CPU-baseline sample (0 disables it)")
     ap.add_argument("--side", type=int, default=1024,
                     help="lattice side of the crossing workload (1024 -> 1,048,576 agents)")
-    ap.add_argument("--cell-size", type=float, default=1.5,
-                    help="grid cell size in m (1.5 = R_n/2, the fastest measured for this "
-                         "workload; 0 = library default R_n)")
+    ap.add_argument("--cell-size", type=float, default=0.6,
+                    help="grid cell size in m (0.6 = R_n/5, the fastest of a sweep over "
+                         "{3, 2, 1.5, 1, 0.75, 0.6, 0.5} m for this workload; 0 = library "
+                         "default R_n)")
     ap.add_argument("--batched-steps", type=int, default=100,
                     help="graph-captured steps of the 512-scene batched form (0 skips it)")
     ap.add_argument("--no-adjoint", dest="adjoint", action="store_false",

@@ -21,7 +21,7 @@ import torch
 
 from . import orca
 
-FACTORS = (1.0, 0.5, 1.0 / 3.0, 0.25)
+FACTORS = (1.0, 0.5, 1.0 / 3.0, 0.25, 0.2)
 MODES = (0, 1)
 
 
