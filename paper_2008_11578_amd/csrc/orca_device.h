@@ -33,6 +33,7 @@ __device__ __forceinline__ float det2(float ax, float ay, float bx, float by)
 }
 
 
+
 // Squared distance in double from FP32 positions, each operation rounded
 // separately (no fused multiply-add): the neighbour order is defined on it.
 __device__ __forceinline__ double nb_key(float xi, float yi, float xj, float yj)

@@ -8,8 +8,14 @@ and radii by one ulp; an agent whose oracle velocity moves by more than
 ``COND_TOL`` under such perturbations sits on a regime boundary (LP2/LP3
 flip, nearly parallel active lines, arc/leg switch, non-unique LP3
 minimiser) where FP32 rounding legitimately selects a different answer.
-Such an agent must still hold a valid answer to the oracle's FP64 problem
-(`valid_answer`); these agents are counted and their share is bounded.
+A second probe covers the rounding of the FP32 path itself: an agent whose
+oracle LP answer moves by more than ``COND_TOL`` when each component of its
+own half-planes is perturbed by a relative 1e-6 (a few FP32 ulps, the error
+of half-planes formed in FP32) is ill-conditioned as well -- its LP path
+(which line first fails, which interval end binds, which LP3 boundary wins)
+is decided below FP32 resolution.  Such an agent must still hold a valid
+answer to the oracle's FP64 problem (`valid_answer`); these agents are
+counted and their share is bounded.
 """
 from __future__ import annotations
 
@@ -71,6 +77,27 @@ def oracle_sensitivity(state_np, params, base, reps=2):
     return sens
 
 
+def line_sensitive(o, st, idx, reps=4, rel=1e-6, seed=77):
+    """For agents `idx`: whether the oracle LP answer on the agent's own
+    half-planes moves by more than COND_TOL when every line component is
+    scaled by (1 + U(-rel, rel))."""
+    rng = np.random.default_rng(seed)
+    out = np.zeros(len(idx), bool)
+    vmax = np.asarray(st["max_speed"], np.float64)
+    for k, a in enumerate(idx):
+        m = int(o["cnt"][a])
+        lines = o["lines"][a, :m].astype(np.float64)
+        pref = o["pref"][a]
+        v0, _ = oracle.lp_full(lines, float(np.float32(vmax[a])), pref)
+        worst = 0.0
+        for _ in range(reps):
+            lp = lines * (1.0 + rng.uniform(-rel, rel, size=lines.shape))
+            v1, _ = oracle.lp_full(lp, float(np.float32(vmax[a])), pref)
+            worst = max(worst, float(np.hypot(*(v1 - v0))))
+        out[k] = worst > COND_TOL
+    return out
+
+
 def penetration(lines, cnt, vx, vy):
     """max_j det(d_j, q_j - v) over each agent's valid lines (-inf if none)."""
     q = lines[:, :, 0:2]
@@ -122,6 +149,10 @@ def compare_step(state_np, params, *, require_all=False, max_ill_frac=0.01, reps
     if bad.any() and not require_all:
         sens = oracle_sensitivity(st, params, o, reps=reps)
         ill = sens > COND_TOL
+        cand = np.nonzero(bad & ~ill)[0]
+        if cand.size:
+            ill[cand] = line_sensitive(o, st, cand)
+            rep["n_line_sensitive"] = int(ill[cand].sum())
         rep["n_ill"] = int(ill.sum())
         rep["n_bad_ill"] = int((bad & ill).sum())
         vmax = np.asarray(st["max_speed"], np.float64)
