@@ -34,6 +34,7 @@ __device__ __forceinline__ float det2(float ax, float ay, float bx, float by)
 
 
 
+
 // Squared distance in double from FP32 positions, each operation rounded
 // separately (no fused multiply-add): the neighbour order is defined on it.
 __device__ __forceinline__ double nb_key(float xi, float yi, float xj, float yj)
@@ -58,7 +59,7 @@ __device__ __forceinline__ double nb_key(float xi, float yi, float xj, float yj)
 // running count reaches k is the threshold: every candidate of a lower bin is
 // among the k nearest and the rest of the k nearest lie in bin b*.
 // Pass 2 visits only the circle that holds bins <= b* and appends their
-// candidates to the lane's LDS column; a bitonic network over registers then
+// candidates to the lane's LDS column; a sorting network over registers then
 // orders them.  Buffer entries are (float(key) bits << 32 | cell-order
 // position): a strict order of the FP32-rounded keys implies the same order
 // of the FP64 keys (rounding is monotone); equal FP32 keys among the entries
@@ -187,28 +188,36 @@ __device__ __forceinline__ bool row_range(const GridMeta &g, const uint32_t *__r
     return a < b;
 }
 
-// Bitonic sorting network over N (a power of two) 64-bit keys held in
-// registers, ascending; every index is a compile-time constant.
+// Sorting network over N (a power of two) 64-bit keys held in registers,
+// ascending; every index is a compile-time constant.
 template <int K>
 struct SortNet {
     static constexpr int N = K <= 8 ? 16 : (K <= 24 ? 32 : 64);
 };
 
 template <int N>
-__device__ __forceinline__ void bitonic_sort(uint64_t (&e)[N])
+__device__ __forceinline__ void cas(uint64_t (&e)[N], int i, int l)
+{
+    const uint64_t a = e[i], b = e[l];
+    const bool sw = b < a;
+    e[i] = sw ? b : a;
+    e[l] = sw ? a : b;
+}
+
+// Batcher's odd-even merge sort (191 comparators for 32 keys against the
+// bitonic network's 240); the loops run at compile time.
+template <int N>
+__device__ __forceinline__ void sort_network(uint64_t (&e)[N])
 {
 #pragma unroll
-    for (int k = 2; k <= N; k <<= 1) {
+    for (int p = 1; p < N; p += p) {
 #pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int k = p; k > 0; k /= 2) {
 #pragma unroll
-            for (int i = 0; i < N; ++i) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const uint64_t a = e[i], b = e[l];
-                    const bool sw = ((i & k) == 0) ? (b < a) : (a < b);
-                    e[i] = sw ? b : a;
-                    e[l] = sw ? a : b;
+            for (int j = k % p; j + k < N; j += k + k) {
+#pragma unroll
+                for (int i = 0; i < k; ++i) {
+                    if ((i + j) / (p + p) == (i + j + k) / (p + p)) cas<N>(e, i + j, i + j + k);
                 }
             }
         }
@@ -340,7 +349,7 @@ __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
             uint64_t e[N];
 #pragma unroll
             for (int p = 0; p < N; ++p) e[p] = p < (int)take ? buf[buf_idx<BLOCK>(p, tid)] : ~0ull;
-            bitonic_sort<N>(e);
+            sort_network<N>(e);
             bool tie = false;
 #pragma unroll
             for (int p = 0; p + 1 < N; ++p)
