@@ -188,6 +188,29 @@ def crossing(side_count: int, side: float, seed: int, *, jitter: float = 0.04,
                    np.zeros(n, np.uint8), steps)
 
 
+def head_on_pairs(pairs: int = 16, gap: float = 15.0, offset: float = 0.2,
+                  spacing: float = 40.0) -> Scenario:
+    """`pairs` isolated pedestrian-vehicle encounters: a pedestrian walking +x
+    at 1.5 m/s and a vehicle driving -x at 6 m/s, `gap` metres apart with a
+    lateral offset of `offset` (less than r_p + r_v, so without avoidance they
+    collide).  Pairs are `spacing` metres apart, beyond each other's neighbour
+    distance.  Preferred velocities equal the current ones (pref_is_goal = 0),
+    so any change of velocity is avoidance."""
+    k = np.arange(pairs, dtype=np.float64)
+    px = np.stack([np.zeros(pairs), np.full(pairs, gap)], 1).ravel()
+    py = np.stack([k * spacing, k * spacing + offset], 1).ravel()
+    vx = np.tile([1.5, -6.0], pairs)
+    n = 2 * pairs
+    return Scenario(name="head_on_pairs", params=Params(dt=0.05, time_horizon=2.0,
+                                                        neighbor_dist=10.0, max_neighbors=4,
+                                                        pref_is_goal=0),
+                    px=_f32(px), py=_f32(py), vx=_f32(vx), vy=np.zeros(n, np.float32),
+                    pref_x=_f32(vx), pref_y=np.zeros(n, np.float32),
+                    radius=_f32(np.tile([0.3, 1.5], pairs)),
+                    max_speed=_f32(np.tile([1.5, 6.0], pairs)),
+                    cls=np.tile(np.array([0, 1], np.uint8), pairs), steps=80)
+
+
 def c3_crossing(seed: int = 3, side_count: int = 1024) -> Scenario:
     """1,048,576 pedestrians, four crossing flows in 700 x 700 m (about
     2.14 agents/m^2); r 0.3 m, v_max 1.5 m/s, dt 0.1 s, tau 2 s, neighbour

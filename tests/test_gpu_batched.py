@@ -10,7 +10,7 @@ import pytest
 import oracle
 from paper_2008_11578_amd import scenarios
 
-from parity import V_TOL, as_dict
+from parity import V_TOL, as_dict, compare_step
 
 pytestmark = pytest.mark.gpu
 
@@ -154,3 +154,77 @@ def test_graph_replay_equals_eager():
         # eager work between replays
         orca.step_batched(e0, b, ws, out=e1)
         torch.cuda.synchronize()
+
+
+def test_batched_per_scene_responsibility_matches_plain_steps():
+    """Scenes that differ only in f (including sums other than 1) step exactly
+    as the plain step does with each table."""
+    import dataclasses
+    import torch
+    from paper_2008_11578_amd import orca, sweeps
+    sc = scenarios.random_state(3000, 60.0, seed=21, n_vehicles=150)
+    tables = [sweeps.table(0.5, 1.0, 0.0, 0.5), sweeps.table(0.5, 0.5, 0.5, 0.5),
+              sweeps.table(0.25, 0.0, 0.0, 0.25), sweeps.table(1.0, 1.0, 1.0, 1.0)]
+    S, n = len(tables), sc.n
+    cat = {k: np.concatenate([getattr(sc, k)] * S) for k in sc.arrays()}
+    off = np.arange(S + 1, dtype=np.int32) * n
+    prm = [dataclasses.replace(sc.params, f=t) for t in tables]
+    st = orca.State.from_arrays(cat)
+    out = orca.step_batched(st, orca.Batch(off, prm), orca.Workspace(st.n, n_scenes=S))
+    torch.cuda.synchronize()
+    for s in range(S):
+        o1 = orca.step(orca.State.from_arrays(sc), prm[s], orca.Workspace(n))
+        torch.cuda.synchronize()
+        for k in ("vx", "vy"):
+            assert torch.equal(getattr(out, k)[s * n:(s + 1) * n], getattr(o1, k)), (s, k)
+    # the tables really differ in effect
+    assert not torch.equal(out.vx[:n], out.vx[n:2 * n])
+
+
+def test_batched_per_scene_responsibility_matches_oracle():
+    """Oracle parity for each table, sums other than 1 included."""
+    import dataclasses
+    from paper_2008_11578_amd import sweeps
+    sc = scenarios.random_state(2000, 50.0, seed=22, n_vehicles=100)
+    for t in (sweeps.table(0.25, 0.75, 0.75, 0.25), sweeps.table(1.0, 1.0, 1.0, 1.0)):
+        compare_step(as_dict(sc), dataclasses.replace(sc.params, f=t))
+
+
+def test_responsibility_sweep_head_on():
+    """Isolated head-on pedestrian-vehicle encounters under four tables.
+    f_{p|v} + f_{v|p} = 1 (either side takes all, or equal shares): no pair
+    ever overlaps by more than rounding (with equal shares the discs end up
+    touching, 1e-5 m deep).  Both zero: nobody turns, every velocity stays exactly as it
+    was, and every pair collides.  With f_{p|v} = 0 the pedestrian's
+    preferred velocity lies on its own half-plane's boundary, so it walks on
+    unchanged."""
+    from paper_2008_11578_amd import scenarios as scn, sweeps
+    sc = scn.head_on_pairs()
+    tabs = [sweeps.table(0.5, 0.0, 1.0, 0.5), sweeps.table(0.5, 0.5, 0.5, 0.5),
+            sweeps.table(0.5, 0.0, 0.0, 0.5), sweeps.table(0.5, 1.0, 0.0, 0.5)]
+    res = sweeps.run(tabs, sc, steps=sc.steps, reach=3.0)
+    print([(r["f"], r["min_clearance"], r["worst_overlap_pairs"], r["mean_speed_ped"],
+            r["mean_speed_veh"]) for r in res])
+    vehicle_all, shared, nobody, ped_all = res
+    for r in (vehicle_all, shared, ped_all):
+        assert r["min_clearance"] > -1e-4
+    assert vehicle_all["worst_overlap_pairs"] == 0
+    assert nobody["worst_overlap_pairs"] == 16 and nobody["min_clearance"] < -1.0
+    assert nobody["mean_speed_ped"] == 1.5 and nobody["mean_speed_veh"] == 6.0
+    assert vehicle_all["mean_speed_ped"] == 1.5
+    assert all(r["lp3_share"] >= 0 for r in res)
+
+
+def test_responsibility_sweep_crowd_runs():
+    """A mixed crowd under two tables: the sweep driver's statistics are
+    well formed."""
+    from paper_2008_11578_amd import scenarios as scn, sweeps
+    sc = scn.uniform_square(1500, 45.0, seed=23, n_vehicles=75,
+                            params=scn.Params(dt=0.05, neighbor_dist=5.0, max_neighbors=16))
+    res = sweeps.run([sweeps.table(0.5, 1.0, 0.0, 0.5), sweeps.table(0.5, 0.0, 0.0, 0.5)], sc,
+                     steps=20)
+    for r in res:
+        assert 0 <= r["lp3_share"] <= 1
+        assert 0 <= r["final_overlap_pairs"] <= r["worst_overlap_pairs"]
+        assert r["worst_overlap_agents"] <= sc.n and np.isfinite(r["min_clearance"])
+        assert 0 < r["mean_speed_ped"] <= 1.5 + 1e-6 and 0 < r["mean_speed_veh"] <= 6 + 1e-5

@@ -263,3 +263,34 @@ def test_batched_equals_per_scene(oracle_mod):
         o1 = oracle_mod.step(p, prm[s])
         for k in ("px", "py", "vx", "vy", "status"):
             np.testing.assert_array_equal(ob[k][off[s]:off[s + 1]], o1[k])
+
+
+def test_responsibility_sum_below_one_loses_the_guarantee(oracle_mod):
+    """With f_{A|B} + f_{B|A} = 1/2 both agents may satisfy their half-planes
+    and still collide within tau (Sec. 3.1 asks for a sum of at least 1);
+    with the sum at 1 the same pairs never collide."""
+    rng = np.random.default_rng(77)
+    hits = {0.25: 0, 0.5: 0}
+    tried = 0
+    for _ in range(1500):
+        R_a, R_b = 0.3, 0.3
+        dist = rng.uniform(0.8, 3.0)
+        ang = rng.uniform(0, 2 * math.pi)
+        pb = (dist * math.cos(ang), dist * math.sin(ang))
+        # head towards each other: the relative velocity points at B
+        sp = rng.uniform(0.5, 1.5)
+        va = (sp * math.cos(ang), sp * math.sin(ang))
+        vb = (-va[0], -va[1])
+        st = _pair_state((0, 0), pb, va, vb, va, vb, R_a, R_b, 3.0, 3.0)
+        tried += 1
+        for fv in hits:
+            f = ((fv, fv), (fv, fv))
+            o = oracle_mod.step(st, _params(neighbor_dist=10.0, f=f))
+            if (o["status"] != 0).any():
+                continue
+            P = np.array([st["px"][1], st["py"][1]], float)  # the FP32 positions
+            Vn = np.array([o["vx"][0] - o["vx"][1], o["vy"][0] - o["vy"][1]])
+            if not _no_collision_within_tau(P, Vn, float(F32(R_a)) + float(F32(R_b)), 2.0):
+                hits[fv] += 1
+    assert hits[0.5] == 0
+    assert hits[0.25] > 50, hits
