@@ -50,6 +50,7 @@ extern "C" {
 #define ORCA_EWORKSPACE (-2) /* workspace smaller than orca_workspace_bytes() */
 #define ORCA_EHIP (-3)       /* a HIP launch reported an error */
 #define ORCA_ERANGE (-4)     /* max_neighbors outside 1..ORCA_K_MAX */
+#define ORCA_ENOTSUP (-5)    /* valid request the entry point does not support */
 
 #define ORCA_K_MAX 32
 #define ORCA_N_MAX 268435456  /* agents per call (2^28) of the neighbour search */
@@ -86,6 +87,19 @@ typedef struct {
     int32_t pref_is_goal; /* 1: pref_* are goals, 0: desired velocities */
     float f[2][2];        /* responsibility f[class_self][class_other] (Sec. 3.1) */
     float par_eps;        /* parallel-line tolerance of the LP, e.g. 1e-5 */
+    float accel[2];       /* acceleration cap per class [m/s^2], >= 0; 0 = none.
+                             Sec. 5 names acceleration-limited vehicles as an
+                             extension adding linear constraints of the agent's
+                             own motion to the same LP.  With a > 0 the new
+                             velocity must lie in the regular octagon inscribed
+                             in the disc of radius a*dt about the current
+                             velocity (scaled onto the speed circle first when
+                             outside it); its 8 edges are hard constraints:
+                             they precede the ORCA lines in LP2 and LP3 never
+                             relaxes them.  (Should LP2 fail on them, which
+                             only rounding can cause, the octagon's centre is
+                             taken.)  orca_step_backward rejects a > 0 with
+                             ORCA_ENOTSUP. */
 } orca_params;
 
 /* Bytes of workspace needed for n agents (plain step / grid), or for a
@@ -145,8 +159,13 @@ typedef struct {
     int32_t mode;                 /* 0: persistent kernel with per-XCD tile queues
                                      (default); 1: one workgroup per tile */
     int32_t *error_flag;          /* DEVICE, nullable: set to 1 (never cleared) when
-                                     an offset or a scene's parameters are invalid;
-                                     the kernels clamp every index regardless */
+                                     an offset or a scene's parameters are invalid
+                                     (including an accel cap > 0 while has_accel
+                                     is 0); the kernels clamp every index
+                                     regardless */
+    int32_t has_accel;            /* HOST: 1 if any scene has accel[c] > 0 (selects
+                                     the kernel with acceleration lines; without it
+                                     caps are ignored and flagged), else 0 */
 } orca_batch;
 
 /* One ORCA step of every scene of a batch.  n is the total agent count; the

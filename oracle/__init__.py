@@ -41,7 +41,8 @@ def build(force: bool = True) -> str:
 class _OParams(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("tau", ctypes.c_double), ("rn", ctypes.c_double),
                 ("k", ctypes.c_int32), ("pref_is_goal", ctypes.c_int32),
-                ("f", (ctypes.c_double * 2) * 2), ("eps", ctypes.c_double)]
+                ("f", (ctypes.c_double * 2) * 2), ("eps", ctypes.c_double),
+                ("accel", ctypes.c_double * 2)]
 
 
 _lib = None
@@ -82,6 +83,11 @@ def lib():
         L.oracle_overlap_stats.restype = ctypes.c_int
         L.oracle_overlap_stats.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 3 + \
             [ctypes.c_float, ctypes.c_void_p]
+        L.oracle_lp_full_hard.restype = ctypes.c_int
+        L.oracle_lp_full_hard.argtypes = [ctypes.c_int, ctypes.c_int, dp] + \
+            [ctypes.c_double] * 6 + [dp]
+        L.oracle_accel_lines.restype = ctypes.c_int
+        L.oracle_accel_lines.argtypes = [ctypes.c_double] * 5 + [dp]
         L.oracle_set_threads.restype = ctypes.c_int
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_step_batched.restype = ctypes.c_int
@@ -175,6 +181,13 @@ def make_params(params) -> _OParams:
         for b in range(2):
             p.f[a][b] = _f32d(f[a][b])
     p.eps = _f32d(g("par_eps"))
+    try:
+        acc = g("accel")
+    except (AttributeError, KeyError):
+        acc = None
+    acc = (0.0, 0.0) if acc is None else acc
+    for c in range(2):
+        p.accel[c] = _f32d(acc[c])
     return p
 
 
@@ -215,6 +228,29 @@ def lp_full(lines, vmax, opt, eps=1e-5):
     if fail < 0:
         raise ValueError("oracle_lp_full: bad arguments")
     return np.array(v[:]), fail
+
+
+def lp_full_hard(lines, n_hard, vmax, opt, centre, eps=1e-5):
+    """LP2/LP3 with the first `n_hard` lines never relaxed (acceleration
+    lines); a failure among them takes v = centre.  Returns (v, fail)."""
+    lines = np.ascontiguousarray(lines, dtype=np.float64).reshape(-1, 4)
+    v = (ctypes.c_double * 2)()
+    fail = lib().oracle_lp_full_hard(lines.shape[0], int(n_hard),
+                                     lines.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     float(vmax), float(opt[0]), float(opt[1]), float(eps),
+                                     float(centre[0]), float(centre[1]), v)
+    if fail < 0:
+        raise ValueError("oracle_lp_full_hard: bad arguments")
+    return np.array(v[:]), fail
+
+
+def accel_lines(v, vmax, accel, dt):
+    """The acceleration lines (8 x 4, or 0 x 4 when accel <= 0) of an agent
+    with current velocity v."""
+    out = (ctypes.c_double * 32)()
+    m = lib().oracle_accel_lines(float(v[0]), float(v[1]), float(vmax), float(accel), float(dt),
+                                 out)
+    return np.array(out[:]).reshape(8, 4)[:m]
 
 
 def knn(px, py, neighbor_dist, k):

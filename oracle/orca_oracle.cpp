@@ -35,6 +35,8 @@
  *    largest penetration.
  *  - desired velocity and update: Sec. 3 / Sec. 4 (velocity toward the goal
  *    scaled to the speed; all agents updated simultaneously, explicit Euler).
+ *  - acceleration limit: Sec. 5 (vehicles whose own motion limits add
+ *    linear constraints to the same LP); see accel_lines.
  *
  * Gradient (not in the paper; the differentiable form of the step): every
  * function of one agent's update is a template over its scalar type.  With
@@ -59,6 +61,7 @@
 #include <omp.h>
 
 #define ORACLE_K_MAX 64
+#define ORACLE_HARD 8 /* acceleration lines of an acceleration-limited agent */
 #define ORACLE_NWORK 12
 
 namespace {
@@ -151,6 +154,7 @@ struct OParams {
     int32_t pref_is_goal;
     double f[2][2];
     double eps;
+    double accel[2]; /* acceleration cap per class [m/s^2]; 0 = none */
 };
 
 /* ------------------------------------------------------------------------ */
@@ -396,22 +400,27 @@ int lp2_mode(const Line<T> *L, int m, double vmax, T ox, T oy, int mode, T tx, T
 /* current level, v is re-solved in the region where no earlier line        */
 /* penetrates more than line i does (boundaries of delta_j = delta_i),      */
 /* pushing v as far as possible into line i's permitted side.               */
+/* The first nh lines are hard (the agent's own motion limits): they are    */
+/* never relaxed, i.e. they enter every re-solve unchanged and the max runs */
+/* over lines nh..m-1 only.                                                 */
 /* w: re-solved lines, boundary lines built, checked, re-solved, inner.     */
 /* ------------------------------------------------------------------------ */
 template <class T>
-void lp3(const Line<T> *L, int m, int fail, double vmax, T tx, T ty, double eps, T *vx, T *vy,
-         int64_t *w, Trace &tr)
+void lp3(const Line<T> *L, int m, int nh, int fail, double vmax, T tx, T ty, double eps, T *vx,
+         T *vy, int64_t *w, Trace &tr)
 {
-    Line<T> proj[ORACLE_K_MAX];
+    Line<T> proj[ORACLE_K_MAX + ORACLE_HARD];
     T level = 0.0;
     T x = *vx, y = *vy;
-    for (int i = fail; i < m; ++i) {
+    for (int i = fail > nh ? fail : nh; i < m; ++i) {
         const Line<T> *li = &L[i];
         if (val(det2(li->dx, li->dy, li->qx - x, li->qy - y)) <= val(level)) continue;
         ++w[0];
         tr.mix(2000 + i);
         int np = 0;
-        for (int j = 0; j < i; ++j) {
+        /* hard lines stay constraints as they are */
+        for (int j = 0; j < nh; ++j) proj[np++] = L[j];
+        for (int j = nh; j < i; ++j) {
             const Line<T> *lj = &L[j];
             const T dij = det2(li->dx, li->dy, lj->dx, lj->dy);
             T ptx, pty;
@@ -460,12 +469,58 @@ struct AgentIn {
     T npx[ORACLE_K_MAX], npy[ORACLE_K_MAX], nvx[ORACLE_K_MAX], nvy[ORACLE_K_MAX];
 };
 
+/* ------------------------------------------------------------------------ */
+/* Acceleration limit (Sec. 5 names acceleration-limited and non-holonomic  */
+/* vehicles as an extension whose motion limits add linear constraints to  */
+/* the same LP).  Reading: within one step the velocity can change by at    */
+/* most a dt, so the new velocity must lie in the disc of radius a dt about */
+/* the current velocity c -- taken scaled onto the speed circle when it lies */
+/* outside it, so that the two regions always meet.  The disc is replaced   */
+/* by the regular octagon inscribed in it (everything the octagon allows    */
+/* respects the limit): edge k has outward unit normal n_k at angle k pi/4  */
+/* and lies a dt cos(pi/8) from c, i.e. the constraint n_k . (v - c) <= h.  */
+/* As a line: q = c + h n_k, d = (-n_k.y, n_k.x) (inward normal -n_k).      */
+/* The eight lines are hard: they precede the ORCA lines in LP2 and LP3     */
+/* never relaxes them.  Returns the number of lines written (0 or 8).       */
+/* ------------------------------------------------------------------------ */
+template <class T>
+void accel_centre(T vx, T vy, double vmax, T *cx, T *cy)
+{
+    *cx = vx;
+    *cy = vy;
+    const T v2 = vx * vx + vy * vy;
+    if (val(v2) > vmax * vmax) {
+        const T s = vmax / sqrt_(v2);
+        *cx = vx * s;
+        *cy = vy * s;
+    }
+}
+
+template <class T>
+int accel_lines(T vx, T vy, double vmax, double accel, double dt, Line<T> *out)
+{
+    if (!(accel > 0.0)) return 0;
+    T cx, cy;
+    accel_centre<T>(vx, vy, vmax, &cx, &cy);
+    const double h = accel * dt * std::cos(M_PI / 8.0);
+    for (int k = 0; k < ORACLE_HARD; ++k) {
+        const double nx = std::cos(k * M_PI / 4.0), ny = std::sin(k * M_PI / 4.0);
+        out[k].qx = cx + h * nx;
+        out[k].qy = cy + h * ny;
+        out[k].dx = T(-ny);
+        out[k].dy = T(nx);
+    }
+    return ORACLE_HARD;
+}
+
 template <class T>
 int agent_update(const AgentIn<T> &a, int self, double r, int cls, double vmax, int m,
                  const int32_t *nb, const double *radius, const uint8_t *klass, const OParams &prm,
                  T *vx_out, T *vy_out, int64_t *w, Trace &tr)
 {
-    Line<T> L[ORACLE_K_MAX];
+    Line<T> L[ORACLE_K_MAX + ORACLE_HARD];
+    const int nh = accel_lines<T>(a.vx, a.vy, vmax, prm.accel[cls & 1], prm.dt, L);
+    if (nh) tr.mix(val(a.vx * a.vx + a.vy * a.vy) > vmax * vmax ? 71 : 70); /* centre clipped */
     T prx, pry;
     if (prm.pref_is_goal) {
         const T gx = a.prx - a.px, gy = a.pry - a.py;
@@ -489,17 +544,27 @@ int agent_update(const AgentIn<T> &a, int self, double r, int cls, double vmax, 
         T hp[8];
         halfplane<T>(a.px, a.py, a.vx, a.vy, r, a.npx[s], a.npy[s], a.nvx[s], a.nvy[s], radius[j],
                      prm.f[cls & 1][klass[j] & 1], a.tau, prm.dt, self < j, hp, tr);
-        L[s].qx = hp[0];
-        L[s].qy = hp[1];
-        L[s].dx = hp[2];
-        L[s].dy = hp[3];
+        L[nh + s].qx = hp[0];
+        L[nh + s].qy = hp[1];
+        L[nh + s].dx = hp[2];
+        L[nh + s].dy = hp[3];
     }
+    const int mt = nh + m;
     T nvx, nvy;
-    const int fail = lp2_mode<T>(L, m, vmax, prx, pry, 0, T(0.0), T(0.0), prm.eps, &nvx, &nvy,
-                                 &w[3], &w[4], &w[5], tr);
+    int fail = lp2_mode<T>(L, mt, vmax, prx, pry, 0, T(0.0), T(0.0), prm.eps, &nvx, &nvy, &w[3],
+                           &w[4], &w[5], tr);
     int st = 0;
-    if (fail < m) {
-        lp3<T>(L, m, fail, vmax, prx, pry, prm.eps, &nvx, &nvy, &w[7], tr);
+    if (fail < nh) {
+        /* the hard lines and the speed disc always meet (the centre of the
+         * octagon lies in the disc), so this is rounding alone; the centre
+         * itself is then taken and LP3 starts from it */
+        accel_centre<T>(a.vx, a.vy, vmax, &nvx, &nvy);
+        tr.mix(60);
+        fail = nh;
+        st = 1;
+    }
+    if (fail < mt) {
+        lp3<T>(L, mt, nh, fail, vmax, prx, pry, prm.eps, &nvx, &nvy, &w[7], tr);
         st = 1;
         w[6] = 1;
     }
@@ -644,7 +709,8 @@ AgentIn<double> agent_in(const DState &S, int i, const int32_t *nb, int m, doubl
 bool params_ok(const OParams *prm)
 {
     return prm && prm->k >= 1 && prm->k <= ORACLE_K_MAX && prm->dt > 0.0 && prm->tau > 0.0 &&
-           prm->rn > 0.0;
+           prm->rn > 0.0 && prm->accel[0] >= 0.0 && prm->accel[1] >= 0.0 &&
+           std::isfinite(prm->accel[0]) && std::isfinite(prm->accel[1]);
 }
 
 /* One synchronous step of every agent of one scene (double state). */
@@ -905,8 +971,47 @@ int oracle_lp_full(int m, const double *lines, double vmax, double ox, double oy
     Trace tr;
     const int fail =
         lp2_mode<double>(L, m, vmax, ox, oy, 0, 0.0, 0.0, eps, &v[0], &v[1], &a, &b, &c, tr);
-    if (fail < m) lp3<double>(L, m, fail, vmax, ox, oy, eps, &v[0], &v[1], w, tr);
+    if (fail < m) lp3<double>(L, m, 0, fail, vmax, ox, oy, eps, &v[0], &v[1], w, tr);
     return fail;
+}
+
+/* The same with the first nh lines hard (acceleration lines); a failure
+ * among them takes v = hard_c (the octagon's centre).  Returns the LP2 fail
+ * index. */
+int oracle_lp_full_hard(int m, int nh, const double *lines, double vmax, double ox, double oy,
+                        double eps, double cx, double cy, double *v)
+{
+    if (m < 0 || nh < 0 || nh > m || m > ORACLE_K_MAX + ORACLE_HARD) return -1;
+    Line<double> L[ORACLE_K_MAX + ORACLE_HARD];
+    load_lines(m, lines, L);
+    int64_t a = 0, b = 0, c = 0, w[5] = {0};
+    Trace tr;
+    int fail =
+        lp2_mode<double>(L, m, vmax, ox, oy, 0, 0.0, 0.0, eps, &v[0], &v[1], &a, &b, &c, tr);
+    const int f0 = fail;
+    if (fail < nh) {
+        v[0] = cx;
+        v[1] = cy;
+        fail = nh;
+    }
+    if (fail < m) lp3<double>(L, m, nh, fail, vmax, ox, oy, eps, &v[0], &v[1], w, tr);
+    return f0;
+}
+
+/* The eight acceleration lines of an agent with current velocity (vx, vy),
+ * speed cap vmax, acceleration cap accel and step dt, as 8 x 4 (qx, qy, dx,
+ * dy); returns the count (0 when accel <= 0). */
+int oracle_accel_lines(double vx, double vy, double vmax, double accel, double dt, double *out)
+{
+    Line<double> L[ORACLE_HARD];
+    const int nh = accel_lines<double>(vx, vy, vmax, accel, dt, L);
+    for (int k = 0; k < nh; ++k) {
+        out[4 * k + 0] = L[k].qx;
+        out[4 * k + 1] = L[k].qy;
+        out[4 * k + 2] = L[k].dx;
+        out[4 * k + 3] = L[k].dy;
+    }
+    return nh;
 }
 
 /* nbr: n x k (row-major, -1 padded), cnt: n.  Returns 0, or -1 on bad args. */

@@ -204,7 +204,7 @@ __device__ __forceinline__ void adjoint_agent(int s, const AdjArgs &a, const Gri
     float vx, vy;
     dev::ActiveSet rec{dev::kFree, -1, -1, -1};
     const int fail = dev::lp2<true>(src, m, vmax, 0, prx, pry, 0.0f, 0.0f, p.eps, vx, vy, &rec);
-    if (fail < m) dev::lp3<true, BLOCK>(lines, tid, m, fail, vmax, prx, pry, p.eps, vx, vy, &rec);
+    if (fail < m) dev::lp3<true, BLOCK>(lines, tid, m, 0, fail, vmax, prx, pry, p.eps, vx, vy, &rec);
 
     // -- cotangent of the new velocity: v' directly and through p' = p + v' dt --
     const float gpx = a.gpx1[i], gpy = a.gpy1[i];

@@ -50,7 +50,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_bbox(const float *__restrict__
                                                        float4 *__restrict__ partial,
                                                        uint32_t *__restrict__ count, int count_len,
                                                        uint32_t *__restrict__ queue,
-                                                       int32_t *__restrict__ error_flag)
+                                                       int32_t *__restrict__ error_flag,
+                                                       int has_accel)
 {
     const int s = blockIdx.x;
     const int a = clamp_off(off[s], n), b = clamp_off(off[s + 1], n);
@@ -76,7 +77,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_bbox(const float *__restrict__
             bad = bad || !(p.dt > 0.0f) || !(p.time_horizon > 0.0f) ||
                   !(p.neighbor_dist > 0.0f) || !(p.cell_size >= 0.0f) ||
                   p.max_neighbors < 1 || p.max_neighbors > ORCA_K_MAX ||
-                  (p.pref_is_goal != 0 && p.pref_is_goal != 1);
+                  (p.pref_is_goal != 0 && p.pref_is_goal != 1) ||
+                  !(p.accel[0] >= 0.0f) || !(p.accel[1] >= 0.0f) ||
+                  !isfinite(p.accel[0]) || !isfinite(p.accel[1]) ||
+                  (!has_accel && (p.accel[0] > 0.0f || p.accel[1] > 0.0f));
             if (bad) atomicOr(error_flag, 1);
         }
     }
@@ -147,21 +151,22 @@ struct BatchArgs {
     float *guess;  // per-agent K-th neighbour distance kept between steps
 };
 
-template <int K, int BLOCK>
+template <int K, int BLOCK, bool ACC>
 __device__ __forceinline__ void batch_agent(const BatchArgs &a, int s, float4 *lines, int tid)
 {
     const int sc = scene_of(a.off, a.S, s);
     const GridMeta g = a.meta[sc];
     const dev::SceneP p = dev::scene_params(a.prm[sc]);
-    dev::step_agent<K, BLOCK>(s, g, p, a.in, a.out, a.start, a.s0, a.s1, lines, tid, a.guess);
+    dev::step_agent<K, BLOCK, ACC>(s, g, p, a.in, a.out, a.start, a.s0, a.s1, lines, tid,
+                                   a.guess);
 }
 
 // Persistent step: wavefronts pop 64-agent tiles, first from their XCD's
 // queue (a contiguous eighth of the tiles), then from the others.
-template <int K, int BLOCK>
+template <int K, int BLOCK, bool ACC>
 __global__ __launch_bounds__(BLOCK) void k_step_batched(BatchArgs a)
 {
-    __shared__ float4 lines[dev::KnnShape<K>::kSlots * BLOCK];
+    __shared__ float4 lines[dev::StepShape<K, ACC>::kSlots * BLOCK];
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int n_tiles = (a.n + kTile - 1) / kTile;
@@ -176,24 +181,24 @@ __global__ __launch_bounds__(BLOCK) void k_step_batched(BatchArgs a)
             t = __shfl(t, 0, kWave);
             if (t >= hi - lo) break;
             const int s = (lo + t) * kTile + lane;
-            if (s < a.n) batch_agent<K, BLOCK>(a, s, lines, tid);
+            if (s < a.n) batch_agent<K, BLOCK, ACC>(a, s, lines, tid);
         }
     }
 }
 
 // Flat form of the same step: one tile per workgroup wave, XCD-aware order.
-template <int K, int BLOCK>
+template <int K, int BLOCK, bool ACC>
 __global__ __launch_bounds__(BLOCK) void k_step_batched_flat(BatchArgs a)
 {
-    __shared__ float4 lines[dev::KnnShape<K>::kSlots * BLOCK];
+    __shared__ float4 lines[dev::StepShape<K, ACC>::kSlots * BLOCK];
     const int tid = threadIdx.x;
     const int s = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + tid;
-    if (s < a.n) batch_agent<K, BLOCK>(a, s, lines, tid);
+    if (s < a.n) batch_agent<K, BLOCK, ACC>(a, s, lines, tid);
 }
 
 // Workgroups of k_step_batched that fit the device at once (cached per
 // instantiation; multiple of the XCD count).
-template <int K, int BLOCK>
+template <int K, int BLOCK, bool ACC>
 int persistent_grid()
 {
     static int cached = 0;
@@ -202,7 +207,8 @@ int persistent_grid()
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_batched<K, BLOCK>, BLOCK, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_batched<K, BLOCK, ACC>, BLOCK,
+                                                     0) !=
         hipSuccess)
         return 0;
     int g = cus * (per_cu > 0 ? per_cu : 1);
@@ -211,32 +217,41 @@ int persistent_grid()
     return g;
 }
 
-template <int K>
-hipError_t launch_step_batched_k(const BatchArgs &a, int mode, hipStream_t stream)
+template <int K, bool ACC>
+hipError_t launch_step_batched_v(const BatchArgs &a, int mode, hipStream_t stream)
 {
     if (mode == 1) {
         const int nb = (a.n + kStepBlock - 1) / kStepBlock;
-        hipLaunchKernelGGL((k_step_batched_flat<K, kStepBlock>), dim3(nb), dim3(kStepBlock), 0,
-                           stream, a);
+        hipLaunchKernelGGL((k_step_batched_flat<K, kStepBlock, ACC>), dim3(nb), dim3(kStepBlock),
+                           0, stream, a);
         return hipGetLastError();
     }
-    const int g = persistent_grid<K, kStepBlock>();
+    const int g = persistent_grid<K, kStepBlock, ACC>();
     if (g <= 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_step_batched<K, kStepBlock>), dim3(g), dim3(kStepBlock), 0, stream, a);
+    hipLaunchKernelGGL((k_step_batched<K, kStepBlock, ACC>), dim3(g), dim3(kStepBlock), 0, stream,
+                       a);
     return hipGetLastError();
+}
+
+template <int K>
+hipError_t launch_step_batched_k(const BatchArgs &a, int mode, bool acc, hipStream_t stream)
+{
+    return acc ? launch_step_batched_v<K, true>(a, mode, stream)
+               : launch_step_batched_v<K, false>(a, mode, stream);
 }
 
 }  // namespace
 
 hipError_t launch_batched(const orca_agents_in &in, const orca_agents_out &out, int n,
                           const int32_t *scene_off, int n_scenes, const orca_params *params,
-                          int k_max, const Layout &L, const Work &w, int32_t *error_flag,
-                          int mode, hipStream_t stream)
+                          int k_max, bool acc, const Layout &L, const Work &w,
+                          int32_t *error_flag, int mode, hipStream_t stream)
 {
     const int S = n_scenes;
     const int nb = (n + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_batch_bbox, dim3(S), dim3(kBlock), 0, stream, in.px, in.py, n, scene_off,
-                       S, params, w.partial, w.count, (int)L.max_cells, w.queue, error_flag);
+                       S, params, w.partial, w.count, (int)L.max_cells, w.queue, error_flag,
+                       acc ? 1 : 0);
     hipLaunchKernelGGL(k_batch_setup, dim3((S + kBlock - 1) / kBlock), dim3(kBlock), 0, stream,
                        w.partial, scene_off, S, n, params, w.meta);
     hipLaunchKernelGGL(k_batch_count, dim3(nb), dim3(kBlock), 0, stream, in.px, in.py, n,
@@ -256,14 +271,14 @@ hipError_t launch_batched(const orca_agents_in &in, const orca_agents_out &out, 
     a.s1 = w.s1;
     a.queue = w.queue;
     a.guess = w.guess;
-    if (k_max <= 4) return launch_step_batched_k<4>(a, mode, stream);
-    if (k_max <= 8) return launch_step_batched_k<8>(a, mode, stream);
-    if (k_max <= 10) return launch_step_batched_k<10>(a, mode, stream);
-    if (k_max <= 12) return launch_step_batched_k<12>(a, mode, stream);
-    if (k_max <= 16) return launch_step_batched_k<16>(a, mode, stream);
-    if (k_max <= 20) return launch_step_batched_k<20>(a, mode, stream);
-    if (k_max <= 24) return launch_step_batched_k<24>(a, mode, stream);
-    return launch_step_batched_k<32>(a, mode, stream);
+    if (k_max <= 4) return launch_step_batched_k<4>(a, mode, acc, stream);
+    if (k_max <= 8) return launch_step_batched_k<8>(a, mode, acc, stream);
+    if (k_max <= 10) return launch_step_batched_k<10>(a, mode, acc, stream);
+    if (k_max <= 12) return launch_step_batched_k<12>(a, mode, acc, stream);
+    if (k_max <= 16) return launch_step_batched_k<16>(a, mode, acc, stream);
+    if (k_max <= 20) return launch_step_batched_k<20>(a, mode, acc, stream);
+    if (k_max <= 24) return launch_step_batched_k<24>(a, mode, acc, stream);
+    return launch_step_batched_k<32>(a, mode, acc, stream);
 }
 
 }  // namespace orca

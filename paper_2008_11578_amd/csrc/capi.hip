@@ -133,6 +133,8 @@ int check_params(const orca_params *p)
         for (int b = 0; b < 2; ++b)
             if (!isfinite(p->f[a][b])) return ORCA_EINVAL;
     if (p->pref_is_goal != 0 && p->pref_is_goal != 1) return ORCA_EINVAL;
+    for (int c = 0; c < 2; ++c)
+        if (!(p->accel[c] >= 0.0f) || !isfinite(p->accel[c])) return ORCA_EINVAL;
     return ORCA_OK;
 }
 
@@ -253,6 +255,7 @@ int orca_step_batched(const orca_agents_in *in, const orca_agents_out *out, int3
     if (batch->n_scenes < 1 || !batch->scene_off || !batch->params) return ORCA_EINVAL;
     if (batch->max_neighbors < 1 || batch->max_neighbors > ORCA_K_MAX) return ORCA_ERANGE;
     if (batch->mode != 0 && batch->mode != 1) return ORCA_EINVAL;
+    if (batch->has_accel != 0 && batch->has_accel != 1) return ORCA_EINVAL;
     if (n == 0) return ORCA_OK;
     int rc = check_in(in);
     if (rc != ORCA_OK) return rc;
@@ -264,8 +267,8 @@ int orca_step_batched(const orca_agents_in *in, const orca_agents_out *out, int3
     if (L.total > ws_bytes) return ORCA_EWORKSPACE;
     const Work w = bind(L, ws);
     if (launch_batched(*in, *out, n, batch->scene_off, batch->n_scenes, batch->params,
-                       batch->max_neighbors, L, w, batch->error_flag, batch->mode,
-                       stream) != hipSuccess)
+                       batch->max_neighbors, batch->has_accel != 0, L, w, batch->error_flag,
+                       batch->mode, stream) != hipSuccess)
         return ORCA_EHIP;
     return ORCA_OK;
 }
@@ -283,6 +286,7 @@ int orca_step_backward(const orca_agents_in *in, int32_t n, const orca_params *p
     if (n < 0 || n > ORCA_N_MAX) return ORCA_EINVAL;
     int rc = check_params(params);
     if (rc != ORCA_OK) return rc;
+    if (params->accel[0] > 0.0f || params->accel[1] > 0.0f) return ORCA_ENOTSUP;
     if (n == 0) return ORCA_OK;
     rc = check_in(in);
     if (rc != ORCA_OK) return rc;
@@ -378,6 +382,7 @@ const char *orca_status_string(int code)
     case ORCA_EWORKSPACE: return "workspace too small";
     case ORCA_EHIP: return "HIP launch error";
     case ORCA_ERANGE: return "max_neighbors outside 1..ORCA_K_MAX";
+    case ORCA_ENOTSUP: return "not supported by this entry point";
     default: return "unknown status";
     }
 }

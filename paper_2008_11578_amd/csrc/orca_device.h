@@ -76,6 +76,17 @@ struct KnnShape {
     static constexpr int kCap = 2 * kSlots;       // buffer entries per lane
 };
 
+// Acceleration lines of an acceleration-limited agent (see accel_lines).
+constexpr int kHard = 8;
+
+// LDS slots per lane of the step: the neighbour buffer, then the half-planes
+// (with ACC, up to kHard acceleration lines ahead of the K ORCA lines).
+template <int K, bool ACC>
+struct StepShape {
+    static constexpr int kLines = ACC ? K + kHard : K;
+    static constexpr int kSlots = KnnShape<K>::kSlots > kLines ? KnnShape<K>::kSlots : kLines;
+};
+
 // Entry e of lane `tid` inside a [slot][BLOCK] float4 array viewed as u64.
 template <int BLOCK>
 __device__ __forceinline__ int buf_idx(int e, int tid)
@@ -475,7 +486,8 @@ struct LdsLines {
 
 // Boundaries of "delta_j(v) <= delta_i(v)" for j < i (least-penetration
 // sub-problem), recomputed on demand from lines i and j.  Lines parallel to i
-// and pointing the same way are not constraints (invalid).
+// and pointing the same way are not constraints (invalid).  With ACC the
+// first nh lines are hard (acceleration lines) and are passed on unchanged.
 // Since delta_j(v) - delta_i(v) = c - det(e, v) with e = d_j - d_i and
 // c = det(d_j, q_j) - det(d_i, q_i), the boundary is det(e/|e|, v) = c/|e|;
 // it is stored through its point nearest the origin, (c/|e|) (-e_y, e_x)/|e|.
@@ -483,16 +495,21 @@ struct LdsLines {
 // (or the midpoint of q_i, q_j for antiparallel lines), but stays well
 // scaled in FP32 when the two lines are nearly parallel and intersect far
 // away from the speed disc.
-template <int BLOCK>
+template <int BLOCK, bool ACC = false>
 struct ProjLines {
     const float4 *L;
     int tid;
     float4 li;
     float ci;    // det(d_i, q_i)
     float eps;
+    int nh;
     __device__ __forceinline__ bool get(int j, float4 &out) const
     {
         const float4 lj = L[j * BLOCK + tid];
+        if (ACC && j < nh) {
+            out = lj;
+            return true;
+        }
         const float dij = det2(li.z, li.w, lj.z, lj.w);
         if (fabsf(dij) <= eps && li.z * lj.z + li.w * lj.w > 0.0f) return false;
         const float ex = lj.z - li.z, ey = lj.w - li.w;
@@ -647,18 +664,20 @@ __device__ __forceinline__ int lp2(const Src &src, int m, float vmax, int mode, 
 // Least penetration (Sec. 3): from LP2's partial result at line `fail`, each
 // later line i whose penetration exceeds the current level re-solves v in the
 // region where no earlier line penetrates more than line i, as deep into line
-// i's permitted side as possible.
-template <bool REC, int BLOCK>
-__device__ __forceinline__ void lp3(const float4 *L, int tid, int m, int fail, float vmax,
-                                    float tx, float ty, float eps, float &vx, float &vy,
-                                    ActiveSet *rec)
+// i's permitted side as possible.  With ACC the first nh lines are hard: never
+// relaxed, they bound every re-solve as they are.
+template <bool REC, int BLOCK, bool ACC = false>
+__device__ __forceinline__ void lp3(const float4 *L, int tid, int m, int nh, int fail,
+                                    float vmax, float tx, float ty, float eps, float &vx,
+                                    float &vy, ActiveSet *rec)
 {
     float level = 0.0f;
     float x = vx, y = vy;
-    for (int i = fail; i < m; ++i) {
+    const int nhard = ACC ? nh : 0;
+    for (int i = fail > nhard ? fail : nhard; i < m; ++i) {
         const float4 li = L[i * BLOCK + tid];
         if (det2(li.z, li.w, li.x - x, li.y - y) <= level) continue;
-        ProjLines<BLOCK> src{L, tid, li, det2(li.z, li.w, li.x, li.y), eps};
+        ProjLines<BLOCK, ACC> src{L, tid, li, det2(li.z, li.w, li.x, li.y), eps, nhard};
         float nx = x, ny = y;
         ActiveSet inner;
         if (lp2<REC>(src, i, vmax, 1, -li.w, li.z, tx, ty, eps, nx, ny, &inner) == i) {
@@ -682,6 +701,7 @@ struct SceneP {
     int k;
     int pref_is_goal;
     float f00, f01, f10, f11;
+    float acc0, acc1;  // acceleration cap per class (0: none)
 };
 
 __device__ __host__ __forceinline__ SceneP scene_params(const orca_params &p)
@@ -697,7 +717,38 @@ __device__ __host__ __forceinline__ SceneP scene_params(const orca_params &p)
     s.f01 = p.f[0][1];
     s.f10 = p.f[1][0];
     s.f11 = p.f[1][1];
+    s.acc0 = p.accel[0];
+    s.acc1 = p.accel[1];
     return s;
+}
+
+// Acceleration limit (Sec. 5: acceleration-limited vehicles add linear
+// constraints of their own motion to the same LP).  Within one step the
+// velocity may change by at most a dt: the new velocity must lie in the
+// regular octagon inscribed in the disc of radius a dt about c, the current
+// velocity scaled onto the speed circle when it lies outside it (so the
+// octagon and the speed disc always meet).  Edge k has outward normal n_k at
+// angle k pi/4 at distance h = a dt cos(pi/8) from c; as a line,
+// q = c + h n_k, d = (-n_k.y, n_k.x).  The lines are hard constraints: they
+// precede the ORCA lines in LP2 and LP3 never relaxes them.
+__device__ __forceinline__ void accel_centre(float vx, float vy, float vmax, float &cx, float &cy)
+{
+    const float v2 = vx * vx + vy * vy;
+    const float sc = v2 > vmax * vmax ? vmax / sqrtf(v2) : 1.0f;
+    cx = vx * sc;
+    cy = vy * sc;
+}
+
+template <int BLOCK>
+__device__ __forceinline__ void write_accel_lines(float cx, float cy, float h, float4 *lines,
+                                                  int tid)
+{
+    constexpr float kS = 0.70710678f;  // cos(pi/4)
+    constexpr float kNx[kHard] = {1.0f, kS, 0.0f, -kS, -1.0f, -kS, 0.0f, kS};
+    constexpr float kNy[kHard] = {0.0f, kS, 1.0f, kS, 0.0f, -kS, -1.0f, -kS};
+#pragma unroll
+    for (int k = 0; k < kHard; ++k)
+        lines[k * BLOCK + tid] = make_float4(cx + h * kNx[k], cy + h * kNy[k], -kNy[k], kNx[k]);
 }
 
 // The half-planes of the agent's m neighbours into its LDS column.
@@ -709,7 +760,8 @@ __device__ __forceinline__ void build_halfplanes(const uint32_t (&pos)[K], int m
                                                  const float4 *__restrict__ s0,
                                                  const float4 *__restrict__ s1, float xi,
                                                  float yi, float vxi, float vyi, float ri, int i,
-                                                 int ci, const SceneP &p, float4 *lines, int tid)
+                                                 int ci, const SceneP &p, float4 *lines, int tid,
+                                                 int base = 0)
 {
     const float fa = ci ? p.f10 : p.f00;  // f[ci][0]
     const float fb = ci ? p.f11 : p.f01;  // f[ci][1]
@@ -729,7 +781,7 @@ __device__ __forceinline__ void build_halfplanes(const uint32_t (&pos)[K], int m
             const int q = q0 + u;
             if (q < K && q < m) {
                 const float f = (__float_as_int(b1[u].z) & 1) ? fb : fa;
-                lines[q * BLOCK + tid] =
+                lines[(base + q) * BLOCK + tid] =
                     halfplane(xi, yi, vxi, vyi, ri, b0[u].x, b0[u].y, b1[u].x, b1[u].y, b0[u].w,
                               f, p.inv_tau, p.inv_dt, i < __float_as_int(b0[u].z));
             }
@@ -753,10 +805,12 @@ __device__ __forceinline__ void desired_velocity(const SceneP &p, float xi, floa
 
 // One whole ORCA step of the agent at cell-order position s: neighbours,
 // half-planes (into the lane's LDS column), LP2, LP3 if needed, update.
-// `lines` is a [max(K, 8)][BLOCK] float4 array; lane `tid` owns column tid.
-// `guess` (caller order, nullable) keeps each agent's K-th neighbour
-// distance between steps (0: none); it only narrows the counting pass.
-template <int K, int BLOCK>
+// `lines` is a [StepShape<K, ACC>::kSlots][BLOCK] float4 array; lane `tid`
+// owns column tid.  `guess` (caller order, nullable) keeps each agent's K-th
+// neighbour distance between steps (0: none); it only narrows the counting
+// pass.  ACC compiles the acceleration lines in (used for agents whose class
+// has a cap).
+template <int K, int BLOCK, bool ACC = false>
 __device__ __forceinline__ void step_agent(int s, const GridMeta &g, const SceneP &p,
                                            const orca_agents_in &in, const orca_agents_out &out,
                                            const uint32_t *__restrict__ start,
@@ -795,15 +849,31 @@ __device__ __forceinline__ void step_agent(int s, const GridMeta &g, const Scene
     for (int q = 0; q < K; ++q) pos[q] = q < m ? entry_pos(buf[buf_idx<BLOCK>(q, tid)]) : 0u;
 
     float prx = in.pref_x[i], pry = in.pref_y[i];
-    build_halfplanes<K, BLOCK>(pos, m, s0, s1, xi, yi, vxi, vyi, ri, i, ci, p, lines, tid);
+    const float acc = ACC ? (ci ? p.acc1 : p.acc0) : 0.0f;
+    const int nh = (ACC && acc > 0.0f) ? kHard : 0;
+    build_halfplanes<K, BLOCK>(pos, m, s0, s1, xi, yi, vxi, vyi, ri, i, ci, p, lines, tid, nh);
+    float cx = 0.0f, cy = 0.0f;
+    if (ACC && nh) {
+        accel_centre(vxi, vyi, vmax, cx, cy);
+        write_accel_lines<BLOCK>(cx, cy, acc * p.dt * 0.92387953f /* cos(pi/8) */, lines, tid);
+    }
     desired_velocity(p, xi, yi, vmax, prx, pry);
 
     LdsLines<BLOCK> src{lines, tid};
+    const int mt = nh + m;
     float vx, vy;
-    const int fail = lp2<false>(src, m, vmax, 0, prx, pry, 0.0f, 0.0f, p.eps, vx, vy, nullptr);
+    int fail = lp2<false>(src, mt, vmax, 0, prx, pry, 0.0f, 0.0f, p.eps, vx, vy, nullptr);
     uint8_t st = 0;
-    if (fail < m) {
-        lp3<false, BLOCK>(lines, tid, m, fail, vmax, prx, pry, p.eps, vx, vy, nullptr);
+    if (ACC && fail < nh) {
+        // the octagon's centre lies in the speed disc, so only rounding can
+        // get here: take the centre and let LP3 start from it
+        vx = cx;
+        vy = cy;
+        fail = nh;
+        st = 1;
+    }
+    if (fail < mt) {
+        lp3<false, BLOCK, ACC>(lines, tid, mt, nh, fail, vmax, prx, pry, p.eps, vx, vy, nullptr);
         st = 1;
     }
     out.vx[i] = vx;

@@ -28,15 +28,16 @@ using dev::buf_idx;
 using dev::KnnShape;
 using dev::knn_select;
 
-template <int K, int BLOCK>
+template <int K, int BLOCK, bool ACC>
 __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, dev::SceneP p)
 {
-    __shared__ float4 lines[dev::KnnShape<K>::kSlots * BLOCK];
+    __shared__ float4 lines[dev::StepShape<K, ACC>::kSlots * BLOCK];
     const int tid = threadIdx.x;
     const int s = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + tid;
     if (s >= a.n) return;
     const GridMeta g = *a.meta;
-    dev::step_agent<K, BLOCK>(s, g, p, a.in, a.out, a.start, a.s0, a.s1, lines, tid, a.guess);
+    dev::step_agent<K, BLOCK, ACC>(s, g, p, a.in, a.out, a.start, a.s0, a.s1, lines, tid,
+                                   a.guess);
 }
 
 template <int K, int BLOCK>
@@ -87,8 +88,13 @@ template <int K>
 void launch_step_k(const StepArgs &a, hipStream_t stream)
 {
     const int nb = (a.n + kStepBlock - 1) / kStepBlock;
-    hipLaunchKernelGGL((k_step<K, kStepBlock>), dim3(nb), dim3(kStepBlock), 0, stream, a,
-                       dev::scene_params(a.prm));
+    // the variant with acceleration lines only when a class has a cap
+    if (a.prm.accel[0] > 0.0f || a.prm.accel[1] > 0.0f)
+        hipLaunchKernelGGL((k_step<K, kStepBlock, true>), dim3(nb), dim3(kStepBlock), 0, stream,
+                           a, dev::scene_params(a.prm));
+    else
+        hipLaunchKernelGGL((k_step<K, kStepBlock, false>), dim3(nb), dim3(kStepBlock), 0, stream,
+                           a, dev::scene_params(a.prm));
 }
 
 template <int K>

@@ -34,7 +34,8 @@ class OrcaParams(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_float), ("time_horizon", ctypes.c_float),
                 ("neighbor_dist", ctypes.c_float), ("cell_size", ctypes.c_float),
                 ("max_neighbors", ctypes.c_int32), ("pref_is_goal", ctypes.c_int32),
-                ("f", (ctypes.c_float * 2) * 2), ("par_eps", ctypes.c_float)]
+                ("f", (ctypes.c_float * 2) * 2), ("par_eps", ctypes.c_float),
+                ("accel", ctypes.c_float * 2)]
 
 
 class AgentsIn(ctypes.Structure):
@@ -48,7 +49,8 @@ class AgentsOut(ctypes.Structure):
 class OrcaBatch(ctypes.Structure):
     _fields_ = [("scene_off", ctypes.c_void_p), ("n_scenes", ctypes.c_int32),
                 ("params", ctypes.c_void_p), ("max_neighbors", ctypes.c_int32),
-                ("mode", ctypes.c_int32), ("error_flag", ctypes.c_void_p)]
+                ("mode", ctypes.c_int32), ("error_flag", ctypes.c_void_p),
+                ("has_accel", ctypes.c_int32)]
 
 
 class Cotangents(ctypes.Structure):
@@ -149,6 +151,13 @@ def make_params(p) -> OrcaParams:
         for b in range(2):
             out.f[a][b] = float(f[a][b])
     out.par_eps = g("par_eps")
+    try:
+        acc = g("accel")
+    except (AttributeError, KeyError):
+        acc = None
+    acc = (0.0, 0.0) if acc is None else acc
+    for c in range(2):
+        out.accel[c] = float(acc[c])
     return out
 
 
@@ -295,12 +304,14 @@ class Batch:
         raw = np.frombuffer(bytes(arr), dtype=np.uint8).copy()
         self.params = torch.as_tensor(raw).to(device)
         self.max_neighbors = max(int(make_params(p).max_neighbors) for p in scene_params)
+        self.has_accel = int(any(make_params(p).accel[c] > 0 for p in scene_params
+                                 for c in range(2)))
         self.mode = int(mode)
         self.error = torch.zeros(1, dtype=torch.int32, device=device)
 
     def c_struct(self) -> OrcaBatch:
         return OrcaBatch(_ptr(self.off), self.n_scenes, _ptr(self.params), self.max_neighbors,
-                         self.mode, _ptr(self.error))
+                         self.mode, _ptr(self.error), self.has_accel)
 
 
 def step_batched(state: State, batch: Batch, ws: Workspace, out: Optional[State] = None,

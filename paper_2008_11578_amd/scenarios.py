@@ -42,6 +42,7 @@ class Params:
     pref_is_goal: int = 1           # 1: pref_x/pref_y hold goals; 0: they hold v_pref
     f: tuple = F_PAPER
     par_eps: float = 1e-5
+    accel: tuple = (0.0, 0.0)      # acceleration cap per class [m/s^2]; 0 = none
 
     def as_dict(self) -> dict:
         return dataclasses.asdict(self)

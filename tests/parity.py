@@ -77,22 +77,51 @@ def oracle_sensitivity(state_np, params, base, reps=2):
     return sens
 
 
-def line_sensitive(o, st, idx, reps=4, rel=1e-6, seed=77):
+def _accel(params):
+    acc = params.get("accel") if isinstance(params, dict) else getattr(params, "accel", None)
+    return (0.0, 0.0) if acc is None else tuple(float(np.float32(a)) for a in acc)
+
+
+def _dt(params):
+    return float(np.float32(params["dt"] if isinstance(params, dict) else params.dt))
+
+
+def hard_lines(st, params, a):
+    """Agent a's acceleration lines (k x 4, k = 0 or 8) and their centre,
+    from the oracle."""
+    acc = _accel(params)[int(st["cls"][a]) & 1]
+    v = (float(st["vx"][a]), float(st["vy"][a]))
+    vmax = float(np.float32(st["max_speed"][a]))
+    h = oracle.accel_lines(v, vmax, acc, _dt(params))
+    sp = float(np.hypot(*v))
+    c = np.array(v) * (vmax / sp if sp > vmax else 1.0)
+    return h, c
+
+
+def line_sensitive(o, st, idx, params=None, reps=4, rel=1e-6, seed=77):
     """For agents `idx`: whether the oracle LP answer on the agent's own
-    half-planes moves by more than COND_TOL when every line component is
-    scaled by (1 + U(-rel, rel))."""
+    lines (acceleration lines, when capped, then half-planes) moves by more
+    than COND_TOL when every line component is scaled by (1 + U(-rel, rel))."""
     rng = np.random.default_rng(seed)
     out = np.zeros(len(idx), bool)
     vmax = np.asarray(st["max_speed"], np.float64)
     for k, a in enumerate(idx):
         m = int(o["cnt"][a])
-        lines = o["lines"][a, :m].astype(np.float64)
+        hard, c = hard_lines(st, params, a) if params is not None else (np.zeros((0, 4)), None)
+        lines = np.concatenate([hard, o["lines"][a, :m].astype(np.float64)])
+        nh = hard.shape[0]
         pref = o["pref"][a]
-        v0, _ = oracle.lp_full(lines, float(np.float32(vmax[a])), pref)
+        vm = float(np.float32(vmax[a]))
+
+        def solve(ls):
+            if nh:
+                return oracle.lp_full_hard(ls, nh, vm, pref, c)[0]
+            return oracle.lp_full(ls, vm, pref)[0]
+
+        v0 = solve(lines)
         worst = 0.0
         for _ in range(reps):
-            lp = lines * (1.0 + rng.uniform(-rel, rel, size=lines.shape))
-            v1, _ = oracle.lp_full(lp, float(np.float32(vmax[a])), pref)
+            v1 = solve(lines * (1.0 + rng.uniform(-rel, rel, size=lines.shape)))
             worst = max(worst, float(np.hypot(*(v1 - v0))))
         out[k] = worst > COND_TOL
     return out
@@ -110,15 +139,23 @@ def penetration(lines, cnt, vx, vy):
     return pen.max(axis=1)
 
 
-def valid_answer(o, g, vmax, tol=V_TOL):
+def valid_answer(o, g, vmax, tol=V_TOL, st=None, params=None):
     """Whether the GPU velocity solves the oracle's own FP64 problem to within
-    `tol`: inside the speed disc, no more penetration than the oracle's
-    answer (least penetration), and, when both sides found a permitted
-    velocity, no farther from the desired velocity than the oracle's."""
+    `tol`: inside the speed disc and the acceleration octagon (when capped),
+    no more penetration of the half-planes than the oracle's answer (least
+    penetration), and, when both sides found a permitted velocity, no
+    farther from the desired velocity than the oracle's."""
     vg_x, vg_y = g["vx"].astype(np.float64), g["vy"].astype(np.float64)
     pen_g = penetration(o["lines"], o["cnt"], vg_x, vg_y)
     pen_o = penetration(o["lines"], o["cnt"], o["vx"], o["vy"])
     speed_ok = np.hypot(vg_x, vg_y) <= vmax * (1 + 1e-5) + 1e-6
+    if params is not None and any(a > 0 for a in _accel(params)):
+        for a in range(len(vg_x)):
+            hard, _ = hard_lines(st, params, a)
+            if hard.shape[0]:
+                ph = penetration(hard[None], np.array([hard.shape[0]]), vg_x[a:a + 1],
+                                 vg_y[a:a + 1])[0]
+                speed_ok[a] &= ph <= tol
     pen_ok = pen_g <= np.maximum(pen_o, 0.0) + tol
     obj_g = np.hypot(vg_x - o["pref"][:, 0], vg_y - o["pref"][:, 1])
     obj_o = np.hypot(o["vx"] - o["pref"][:, 0], o["vy"] - o["pref"][:, 1])
@@ -151,12 +188,12 @@ def compare_step(state_np, params, *, require_all=False, max_ill_frac=0.01, reps
         ill = sens > COND_TOL
         cand = np.nonzero(bad & ~ill)[0]
         if cand.size:
-            ill[cand] = line_sensitive(o, st, cand)
+            ill[cand] = line_sensitive(o, st, cand, params)
             rep["n_line_sensitive"] = int(ill[cand].sum())
         rep["n_ill"] = int(ill.sum())
         rep["n_bad_ill"] = int((bad & ill).sum())
         vmax = np.asarray(st["max_speed"], np.float64)
-        ok = valid_answer(o, g, vmax)
+        ok = valid_answer(o, g, vmax, st=st, params=params)
         rep["n_bad_ill_invalid"] = int((bad & ill & ~ok).sum())
         # ill-conditioned agents must still hold a valid answer
         assert not (bad & ill & ~ok).any(), (rep, np.nonzero(bad & ill & ~ok)[0][:10])

@@ -33,16 +33,17 @@ def test_every_declared_symbol_is_exported(orca_mod):
 
 
 def test_struct_sizes_match_header(orca_mod):
-    assert ctypes.sizeof(orca_mod.OrcaParams) == 4 * 4 + 4 + 4 + 16 + 4
+    assert ctypes.sizeof(orca_mod.OrcaParams) == 4 * 4 + 4 + 4 + 16 + 4 + 8
     assert ctypes.sizeof(orca_mod.AgentsIn) == 9 * 8
     assert ctypes.sizeof(orca_mod.AgentsOut) == 5 * 8
-    assert ctypes.sizeof(orca_mod.OrcaBatch) == 8 + 4 + 4 + 8 + 4 + 4 + 8
+    assert ctypes.sizeof(orca_mod.OrcaBatch) == 8 + 4 + 4 + 8 + 4 + 4 + 8 + 8
 
 
 def test_status_strings(orca_mod):
     assert orca_mod.status_string(0) == "ok"
     assert "invalid" in orca_mod.status_string(-1)
     assert "workspace" in orca_mod.status_string(-2)
+    assert "not supported" in orca_mod.status_string(-5)
     assert orca_mod.status_string(12345) == "unknown status"
     assert "gfx950" in orca_mod.version()
 
@@ -81,6 +82,8 @@ def _out_fake(orca_mod):
     (dict(max_neighbors=0), -4), (dict(max_neighbors=33), -4), (dict(dt=0.0), -1),
     (dict(dt=float("nan")), -1), (dict(time_horizon=-1.0), -1), (dict(neighbor_dist=0.0), -1),
     (dict(cell_size=-1.0), -1), (dict(pref_is_goal=2), -1), (dict(par_eps=-1.0), -1),
+    (dict(accel=(-1.0, 0.0)), -1), (dict(accel=(0.0, float("inf"))), -1),
+    (dict(accel=(0.0, float("nan"))), -1),
 ])
 def test_step_rejects_bad_params(orca_mod, kw, code):
     lib = orca_mod.lib()
@@ -124,7 +127,8 @@ def test_batched_argument_errors(orca_mod):
     lib = orca_mod.lib()
     ain, aout = _in_fake(orca_mod), _out_fake(orca_mod)
     B = orca_mod.OrcaBatch
-    good = dict(scene_off=FAKE, n_scenes=2, params=FAKE, max_neighbors=16, mode=0, error_flag=None)
+    good = dict(scene_off=FAKE, n_scenes=2, params=FAKE, max_neighbors=16, mode=0, error_flag=None,
+                has_accel=0)
 
     def call(n=100, ws_bytes=1 << 30, **kw):
         d = dict(good)
@@ -141,6 +145,7 @@ def test_batched_argument_errors(orca_mod):
     assert call(max_neighbors=0) == -4
     assert call(max_neighbors=40) == -4
     assert call(mode=7) == -1
+    assert call(has_accel=2) == -1
     assert call(ws_bytes=1024) == -2
 
 
@@ -185,3 +190,18 @@ def test_overlap_argument_errors(orca_mod):
     assert lib.orca_overlap_stats(ctypes.byref(ain), 100, 0.0, FAKE, FAKE, need, None) == -1
     assert lib.orca_overlap_stats(ctypes.byref(ain), -1, 5.0, FAKE, FAKE, need, None) == -1
     assert lib.orca_overlap_stats(ctypes.byref(ain), 100, 5.0, FAKE, FAKE, 64, None) == -2
+
+
+def test_backward_rejects_acceleration_caps(orca_mod):
+    lib = orca_mod.lib()
+    ain = _in_fake(orca_mod)
+    g1 = orca_mod.Cotangents(*([FAKE] * 4))
+    g0 = orca_mod.CotangentsOut(*([FAKE] * 7))
+    ok = _params(orca_mod)
+    capped = _params(orca_mod, accel=(0.0, 3.0))
+    need = lib.orca_backward_workspace_bytes(100, 0)
+    assert lib.orca_step_backward(ctypes.byref(ain), 100, ctypes.byref(capped), ctypes.byref(g1),
+                                  ctypes.byref(g0), FAKE, need, None) == -5
+    # the same call without the cap gets past parameter checks (small workspace)
+    assert lib.orca_step_backward(ctypes.byref(ain), 100, ctypes.byref(ok), ctypes.byref(g1),
+                                  ctypes.byref(g0), FAKE, 64, None) == -2

@@ -1,0 +1,144 @@
+"""Acceleration-limited agents on the GPU (Sec. 5: acceleration limits as
+extra linear constraints in the same LP): the HIP path against the FP64
+oracle through the C ABI, the batched form against single-scene steps, and
+the relations to the uncapped step."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2008_11578_amd import scenarios
+
+from parity import as_dict, compare_step, gpu_step
+
+pytestmark = pytest.mark.gpu
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+def _crowd(n, side, seed, veh_share, accel, k=10, dt=0.1):
+    p = scenarios.Params(dt=dt, neighbor_dist=5.0, max_neighbors=k, accel=accel)
+    return scenarios.random_state(n, side, seed=seed, n_vehicles=int(veh_share * n), params=p)
+
+
+@pytest.mark.parametrize("accel,k", [((0.0, 3.0), 10), ((2.0, 3.0), 16), ((0.5, 0.5), 10),
+                                     ((8.0, 1.0), 20)])
+def test_capped_step_matches_oracle(accel, k):
+    sc = _crowd(6000, 70.0, seed=31 + k, veh_share=0.1, accel=accel, k=k)
+    _print("accel", accel, "k", k, "n", sc.n)
+    rep, g, o = compare_step(as_dict(sc), sc.params)
+    _print(rep)
+    # the caps bind: capped agents that changed relative to no cap exist
+    o0 = oracle.step(as_dict(sc), dataclasses.replace(sc.params, accel=(0.0, 0.0)))
+    moved = np.hypot(o["vx"] - o0["vx"], o["vy"] - o0["vy"]) > 1e-3
+    assert moved.sum() > 50
+
+
+def test_capped_step_every_velocity_within_its_octagon():
+    """GPU velocities respect the acceleration lines the oracle forms for
+    each agent (to FP32 rounding)."""
+    from parity import hard_lines
+    sc = _crowd(4000, 60.0, seed=5, veh_share=0.2, accel=(1.0, 2.0))
+    st = as_dict(sc)
+    g = gpu_step(st, sc.params)
+    worst = 0.0
+    for a in range(sc.n):
+        h, _ = hard_lines(st, sc.params, a)
+        q, d = h[:, 0:2], h[:, 2:4]
+        r = q - np.array([g["vx"][a], g["vy"][a]], np.float64)
+        worst = max(worst, float((d[:, 0] * r[:, 1] - d[:, 1] * r[:, 0]).max()))
+    _print("worst hard-line penetration", worst)
+    assert worst <= 1e-5
+
+
+def test_cap_too_large_to_bind_equals_uncapped():
+    sc = _crowd(5000, 60.0, seed=7, veh_share=0.1, accel=(0.0, 0.0))
+    st = as_dict(sc)
+    g0 = gpu_step(st, sc.params)
+    g1 = gpu_step(st, dataclasses.replace(sc.params, accel=(1e6, 1e6)))
+    for k in ("vx", "vy", "px", "py", "status"):
+        np.testing.assert_array_equal(g0[k], g1[k])
+
+
+def test_uncapped_class_unchanged_by_other_class_cap():
+    sc = _crowd(5000, 60.0, seed=8, veh_share=0.1, accel=(0.0, 0.0))
+    st = as_dict(sc)
+    g0 = gpu_step(st, sc.params)
+    g1 = gpu_step(st, dataclasses.replace(sc.params, accel=(0.0, 2.0)))
+    ped = st["cls"] == 0
+    for k in ("vx", "vy"):
+        np.testing.assert_array_equal(g0[k][ped], g1[k][ped])
+    assert not np.array_equal(g0["vx"][~ped], g1["vx"][~ped])
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_batched_caps_equal_single_scene_steps(mode):
+    import torch
+    from paper_2008_11578_amd import orca
+    caps = [(0.0, 0.0), (0.0, 3.0), (1.5, 1.5), (4.0, 0.0)]
+    parts = [_crowd(n, np.sqrt(n / 0.4), seed=40 + s, veh_share=0.1, accel=caps[s % 4])
+             for s, n in enumerate([500, 64, 3000, 1, 1200, 800])]
+    off = np.zeros(len(parts) + 1, np.int32)
+    off[1:] = np.cumsum([p.n for p in parts])
+    cat = {k: np.concatenate([getattr(p, k) for p in parts]) for k in parts[0].arrays()}
+    st = orca.State.from_arrays(cat)
+    b = orca.Batch(off, [p.params for p in parts], mode=mode)
+    assert b.has_accel == 1
+    out = orca.step_batched(st, b, orca.Workspace(st.n, n_scenes=len(parts)))
+    torch.cuda.synchronize()
+    assert int(b.error.item()) == 0
+    for s, p in enumerate(parts):
+        o1 = orca.step(orca.State.from_arrays(p), p.params, orca.Workspace(p.n))
+        torch.cuda.synchronize()
+        for k in ("vx", "vy", "px", "py"):
+            assert torch.equal(getattr(out, k)[off[s]:off[s + 1]], getattr(o1, k)), (s, k)
+
+
+def test_batched_flags_caps_without_the_capped_kernel():
+    import torch
+    from paper_2008_11578_amd import orca
+    sc = _crowd(300, 20.0, seed=3, veh_share=0.1, accel=(0.0, 2.0))
+    st = orca.State.from_arrays(sc)
+    b = orca.Batch(np.array([0, sc.n], np.int32), [sc.params])
+    b.has_accel = 0   # a caller that claims no scene is capped
+    orca.step_batched(st, b, orca.Workspace(st.n, n_scenes=1))
+    torch.cuda.synchronize()
+    assert int(b.error.item()) == 1
+
+
+def test_head_on_vehicle_with_low_cap_brakes_late():
+    """A vehicle with a low cap cannot turn away in time from a pedestrian it
+    is assigned all avoidance of: its velocity changes by at most a dt each
+    step (oracle and GPU agree every step), and the pair ends up closer than
+    without the cap."""
+    from paper_2008_11578_amd import orca
+    import torch
+    sc = scenarios.head_on_pairs(pairs=4)
+    res = {}
+    for acc in (0.0, 1.0):
+        p = dataclasses.replace(sc.params, f=((0.5, 0.0), (1.0, 0.5)), accel=(0.0, acc))
+        st = orca.State.from_arrays(sc)
+        ws = orca.Workspace(sc.n)
+        ost = {k: v.copy() for k, v in sc.arrays().items()}
+        gap = np.inf
+        for t in range(sc.steps):
+            prev = (st.vx.cpu().numpy().copy(), st.vy.cpu().numpy().copy())
+            st = orca.step(st, p, ws)
+            torch.cuda.synchronize()
+            o = oracle.step(ost, p)
+            gv = np.stack([st.vx.cpu().numpy(), st.vy.cpu().numpy()], 1)
+            assert np.abs(gv[:, 0] - o["vx"]).max() < 1e-3 and np.abs(gv[:, 1] - o["vy"]).max() < 1e-3, t
+            if acc > 0:
+                dv = np.hypot(gv[1::2, 0] - prev[0][1::2], gv[1::2, 1] - prev[1][1::2])
+                assert (dv <= acc * float(np.float32(p.dt)) * (1 + 1e-5) + 1e-6).all(), t
+            ost = {k: (st_k.cpu().numpy() if k in ("px", "py", "vx", "vy") else ost[k])
+                   for k, st_k in ((k, getattr(st, k)) for k in ost)}
+            d = np.hypot(ost["px"][0::2] - ost["px"][1::2], ost["py"][0::2] - ost["py"][1::2])
+            gap = min(gap, float((d - 1.8).min()))
+        res[acc] = gap
+    _print("min clearance without / with cap", res)
+    assert res[0.0] > -1e-4
+    assert res[1.0] < res[0.0]
