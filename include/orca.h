@@ -50,7 +50,6 @@ extern "C" {
 #define ORCA_EWORKSPACE (-2) /* workspace smaller than orca_workspace_bytes() */
 #define ORCA_EHIP (-3)       /* a HIP launch reported an error */
 #define ORCA_ERANGE (-4)     /* max_neighbors outside 1..ORCA_K_MAX */
-#define ORCA_ENOTSUP (-5)    /* valid request the entry point does not support */
 
 #define ORCA_K_MAX 32
 #define ORCA_N_MAX 268435456  /* agents per call (2^28) of the neighbour search */
@@ -98,8 +97,9 @@ typedef struct {
                              they precede the ORCA lines in LP2 and LP3 never
                              relaxes them.  (Should LP2 fail on them, which
                              only rounding can cause, the octagon's centre is
-                             taken.)  orca_step_backward rejects a > 0 with
-                             ORCA_ENOTSUP. */
+                             taken.)  orca_step_backward differentiates the
+                             octagon through its centre (a and dt are
+                             constants). */
 } orca_params;
 
 /* Bytes of workspace needed for n agents (plain step / grid), or for a

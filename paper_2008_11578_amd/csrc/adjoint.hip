@@ -14,6 +14,9 @@
 //                     ORCA each involved half-plane through its branch (cutoff
 //                          arc, leg, overlap) to P = p_B - p_A, V = v_A - v_B
 //                          and 1/tau,
+//                     caps an involved acceleration line (q = c + h n_k)
+//                          through its centre c to the agent's own velocity
+//                          (c = v, or v scaled onto the speed circle),
 //                   writing the agent's own cotangents and up to three
 //                   contributions to neighbours into an edge list;
 //   k_edge_*        counting sort of the edges by target, each target summing
@@ -165,7 +168,7 @@ __device__ __forceinline__ void solve2(float g1x, float g1y, float g2x, float g2
     m2 = (g1x * wy - g1y * wx) * id;
 }
 
-template <int K, int BLOCK>
+template <int K, int BLOCK, bool ACC>
 __device__ __forceinline__ void adjoint_agent(int s, const AdjArgs &a, const GridMeta &g,
                                               float4 *lines, int tid)
 {
@@ -186,9 +189,16 @@ __device__ __forceinline__ void adjoint_agent(int s, const AdjArgs &a, const Gri
 #pragma unroll
     for (int q = 0; q < K; ++q)
         pos[q] = q < m ? dev::entry_pos(buf[dev::buf_idx<BLOCK>(q, tid)]) : 0u;
-    dev::build_halfplanes<K, BLOCK>(pos, m, a.s0, a.s1, xi, yi, vxi, vyi, ri, i, ci, p, lines,
-                                    tid);
     const float vmax = a.in.max_speed[i];
+    const float acc = ACC ? (ci ? p.acc1 : p.acc0) : 0.0f;
+    const int nh = (ACC && acc > 0.0f) ? dev::kHard : 0;
+    dev::build_halfplanes<K, BLOCK>(pos, m, a.s0, a.s1, xi, yi, vxi, vyi, ri, i, ci, p, lines,
+                                    tid, nh);
+    float cx = 0.0f, cy = 0.0f;
+    if (ACC && nh) {
+        dev::accel_centre(vxi, vyi, vmax, cx, cy);
+        dev::write_accel_lines<BLOCK>(cx, cy, dev::accel_half_width(acc, p.dt), lines, tid);
+    }
     const float pin_x = a.in.pref_x[i], pin_y = a.in.pref_y[i];
     float prx = pin_x, pry = pin_y;
     dev::desired_velocity(p, xi, yi, vmax, prx, pry);
@@ -203,8 +213,16 @@ __device__ __forceinline__ void adjoint_agent(int s, const AdjArgs &a, const Gri
     dev::LdsLines<BLOCK> src{lines, tid};
     float vx, vy;
     dev::ActiveSet rec{dev::kFree, -1, -1, -1};
-    const int fail = dev::lp2<true>(src, m, vmax, 0, prx, pry, 0.0f, 0.0f, p.eps, vx, vy, &rec);
-    if (fail < m) dev::lp3<true, BLOCK>(lines, tid, m, 0, fail, vmax, prx, pry, p.eps, vx, vy, &rec);
+    const int mt = nh + m;
+    int fail = dev::lp2<true>(src, mt, vmax, 0, prx, pry, 0.0f, 0.0f, p.eps, vx, vy, &rec);
+    if (ACC && fail < nh) {
+        vx = cx;
+        vy = cy;
+        fail = nh;
+        rec.kind = dev::kCentre;
+    }
+    if (fail < mt)
+        dev::lp3<true, BLOCK, ACC>(lines, tid, mt, nh, fail, vmax, prx, pry, p.eps, vx, vy, &rec);
 
     // -- cotangent of the new velocity: v' directly and through p' = p + v' dt --
     const float gpx = a.gpx1[i], gpy = a.gpy1[i];
@@ -218,7 +236,33 @@ __device__ __forceinline__ void adjoint_agent(int s, const AdjArgs &a, const Gri
         lb.qx[e] = lb.qy[e] = lb.nx[e] = lb.ny[e] = 0.0f;
     }
     float pbx = 0.0f, pby = 0.0f;  // cotangent of the desired velocity
+    float cbx = 0.0f, cby = 0.0f;  // cotangent of the acceleration octagon's centre
     auto Lq = [&](int idx) { return lines[idx * BLOCK + tid]; };
+    // Rows of an LP3 sub-problem: line j < nh is a hard line, g = n_j,
+    // r = n_j . q_j; otherwise the equal-penetration boundary of j and i3,
+    // g = n_i3 - n_j, r = n_i3 . q_i3 - n_j . q_j.  For v = G^-1 r the
+    // cotangents are r-bar = mu, g-bar = -mu v with mu = G^-T w; row_bar
+    // scatters them to the lines and returns the share that goes to i3.
+    auto row_g = [&](int j, float nix, float niy, float &gx, float &gy) {
+        const float4 lj = Lq(j);
+        if (ACC && j < nh) {
+            gx = -lj.w;
+            gy = lj.z;
+        } else {
+            gx = nix - (-lj.w);
+            gy = niy - lj.z;
+        }
+    };
+    auto row_bar = [&](int j, float mu) -> float {
+        const float4 lj = Lq(j);
+        const float njx = -lj.w, njy = lj.z;
+        if (ACC && j < nh) {
+            add_line(lb, j, mu * njx, mu * njy, mu * (lj.x - vx), mu * (lj.y - vy));
+            return 0.0f;
+        }
+        add_line(lb, j, -mu * njx, -mu * njy, -mu * (lj.x - vx), -mu * (lj.y - vy));
+        return mu;
+    };
     switch (rec.kind) {
     case dev::kFree:
         pbx = wx;
@@ -265,31 +309,38 @@ __device__ __forceinline__ void adjoint_agent(int s, const AdjArgs &a, const Gri
         add_line(lb, rec.i3, 0.0f, 0.0f, vmax * wx, vmax * wy);
         break;
     case dev::kProjDisc: {
-        const float4 li = Lq(rec.i3), la = Lq(rec.a);
-        const float nix = -li.w, niy = li.z, nax = -la.w, nay = la.z;
-        float m1, m2;
-        solve2(nix - nax, niy - nay, vx, vy, wx, wy, m1, m2);
-        add_line(lb, rec.a, -m1 * nax, -m1 * nay, -m1 * (la.x - vx), -m1 * (la.y - vy));
-        add_line(lb, rec.i3, m1 * nix, m1 * niy, m1 * (li.x - vx), m1 * (li.y - vy));
+        const float4 li = Lq(rec.i3);
+        const float nix = -li.w, niy = li.z;
+        float gax, gay, m1, m2;
+        row_g(rec.a, nix, niy, gax, gay);
+        solve2(gax, gay, vx, vy, wx, wy, m1, m2);
+        const float ms = row_bar(rec.a, m1);
+        if (!ACC || ms != 0.0f)
+            add_line(lb, rec.i3, ms * nix, ms * niy, ms * (li.x - vx), ms * (li.y - vy));
         break;
     }
     case dev::kProjProj: {
-        const float4 li = Lq(rec.i3), la = Lq(rec.a), lc = Lq(rec.b);
-        const float nix = -li.w, niy = li.z, nax = -la.w, nay = la.z, ncx = -lc.w, ncy = lc.z;
-        float ma, mc;
-        solve2(nix - nax, niy - nay, nix - ncx, niy - ncy, wx, wy, ma, mc);
-        add_line(lb, rec.a, -ma * nax, -ma * nay, -ma * (la.x - vx), -ma * (la.y - vy));
-        add_line(lb, rec.b, -mc * ncx, -mc * ncy, -mc * (lc.x - vx), -mc * (lc.y - vy));
-        const float ms = ma + mc;
-        add_line(lb, rec.i3, ms * nix, ms * niy, ms * (li.x - vx), ms * (li.y - vy));
+        const float4 li = Lq(rec.i3);
+        const float nix = -li.w, niy = li.z;
+        float gax, gay, gcx, gcy, ma, mc;
+        row_g(rec.a, nix, niy, gax, gay);
+        row_g(rec.b, nix, niy, gcx, gcy);
+        solve2(gax, gay, gcx, gcy, wx, wy, ma, mc);
+        const float msa = row_bar(rec.a, ma);
+        const float ms = msa + row_bar(rec.b, mc);
+        if (!ACC || ms != 0.0f)
+            add_line(lb, rec.i3, ms * nix, ms * niy, ms * (li.x - vx), ms * (li.y - vy));
         break;
     }
     case dev::kTie: {
         const float4 li = Lq(rec.i3), la = Lq(rec.a);
         const float nix = -li.w, niy = li.z, nax = -la.w, nay = la.z;
-        const float gx = nix - nax, gy = niy - nay;
+        const bool hard = ACC && rec.a < nh;
+        float gx, gy;
+        row_g(rec.a, nix, niy, gx, gy);
         const float G = gx * gx + gy * gy;
-        const float h = nix * li.x + niy * li.y - (nax * la.x + nay * la.y);
+        const float h = hard ? nax * la.x + nay * la.y
+                             : nix * li.x + niy * li.y - (nax * la.x + nay * la.y);
         const float sv = (gx * prx + gy * pry - h) / G;
         const float c = wx * gx + wy * gy;
         pbx = wx - c / G * gx;
@@ -297,10 +348,18 @@ __device__ __forceinline__ void adjoint_agent(int s, const AdjArgs &a, const Gri
         const float hb = c / G;
         const float gbx = -(c / G) * (prx - 2.0f * sv * gx) - sv * wx;
         const float gby = -(c / G) * (pry - 2.0f * sv * gy) - sv * wy;
-        add_line(lb, rec.i3, hb * nix, hb * niy, gbx + hb * li.x, gby + hb * li.y);
-        add_line(lb, rec.a, -hb * nax, -hb * nay, -gbx - hb * la.x, -gby - hb * la.y);
+        if (hard) {
+            add_line(lb, rec.a, hb * nax, hb * nay, gbx + hb * la.x, gby + hb * la.y);
+        } else {
+            add_line(lb, rec.i3, hb * nix, hb * niy, gbx + hb * li.x, gby + hb * li.y);
+            add_line(lb, rec.a, -hb * nax, -hb * nay, -gbx - hb * la.x, -gby - hb * la.y);
+        }
         break;
     }
+    case dev::kCentre:
+        cbx = wx;
+        cby = wy;
+        break;
     default:
         break;
     }
@@ -313,11 +372,16 @@ __device__ __forceinline__ void adjoint_agent(int s, const AdjArgs &a, const Gri
     for (int e = 0; e < kEdges; ++e) {
         int32_t tgt = -1;
         float4 val = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (lb.idx[e] >= 0) {
+        if (ACC && lb.idx[e] >= 0 && lb.idx[e] < nh) {
+            // acceleration line: q = c + h n_k with a constant normal
+            cbx += lb.qx[e];
+            cby += lb.qy[e];
+        } else if (lb.idx[e] >= 0) {
             uint32_t pj = 0u;
+            const int qn = lb.idx[e] - nh;
 #pragma unroll
             for (int q = 0; q < K; ++q)
-                if (q == lb.idx[e]) pj = pos[q];
+                if (q == qn) pj = pos[q];
             const float4 b0 = a.s0[pj];
             const float4 b1 = a.s1[pj];
             const int j = __float_as_int(b0.z);
@@ -337,6 +401,20 @@ __device__ __forceinline__ void adjoint_agent(int s, const AdjArgs &a, const Gri
         }
         a.e_tgt[(int64_t)kEdges * i + e] = tgt;
         a.e_val[(int64_t)kEdges * i + e] = val;
+    }
+    if (ACC && nh) {
+        // c = v, or v (v_max / |v|) when |v| > v_max: Jacobian (v_max/|v|)(I - u u^T)
+        const float v2 = vxi * vxi + vyi * vyi;
+        if (v2 > vmax * vmax) {
+            const float l = sqrtf(v2);
+            const float ux = vxi / l, uy = vyi / l, sc = vmax / l;
+            const float uc = ux * cbx + uy * cby;
+            svx += sc * (cbx - ux * uc);
+            svy += sc * (cby - uy * uc);
+        } else {
+            svx += cbx;
+            svy += cby;
+        }
     }
 
     // -- desired velocity: the pref input itself, or the goal --
@@ -369,15 +447,15 @@ __device__ __forceinline__ void adjoint_agent(int s, const AdjArgs &a, const Gri
     a.e_cnt[i] = 0u;
 }
 
-template <int K, int BLOCK>
+template <int K, int BLOCK, bool ACC>
 __global__ __launch_bounds__(BLOCK) void k_adjoint(AdjArgs a)
 {
-    __shared__ float4 lines[dev::KnnShape<K>::kSlots * BLOCK];
+    __shared__ float4 lines[dev::StepShape<K, ACC>::kSlots * BLOCK];
     const int tid = threadIdx.x;
     const int s = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + tid;
     if (s >= a.n) return;
     const GridMeta g = *a.meta;
-    adjoint_agent<K, BLOCK>(s, a, g, lines, tid);
+    adjoint_agent<K, BLOCK, ACC>(s, a, g, lines, tid);
 }
 
 // Edges by target: count and rank.
@@ -481,7 +559,12 @@ template <int K>
 void launch_adjoint_k(const AdjArgs &a, hipStream_t stream)
 {
     const int nb = (a.n + kAdjBlock - 1) / kAdjBlock;
-    hipLaunchKernelGGL((k_adjoint<K, kAdjBlock>), dim3(nb), dim3(kAdjBlock), 0, stream, a);
+    if (a.p.acc0 > 0.0f || a.p.acc1 > 0.0f)
+        hipLaunchKernelGGL((k_adjoint<K, kAdjBlock, true>), dim3(nb), dim3(kAdjBlock), 0, stream,
+                           a);
+    else
+        hipLaunchKernelGGL((k_adjoint<K, kAdjBlock, false>), dim3(nb), dim3(kAdjBlock), 0, stream,
+                           a);
 }
 
 }  // namespace

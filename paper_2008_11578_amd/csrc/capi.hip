@@ -286,7 +286,6 @@ int orca_step_backward(const orca_agents_in *in, int32_t n, const orca_params *p
     if (n < 0 || n > ORCA_N_MAX) return ORCA_EINVAL;
     int rc = check_params(params);
     if (rc != ORCA_OK) return rc;
-    if (params->accel[0] > 0.0f || params->accel[1] > 0.0f) return ORCA_ENOTSUP;
     if (n == 0) return ORCA_OK;
     rc = check_in(in);
     if (rc != ORCA_OK) return rc;
@@ -382,7 +381,6 @@ const char *orca_status_string(int code)
     case ORCA_EWORKSPACE: return "workspace too small";
     case ORCA_EHIP: return "HIP launch error";
     case ORCA_ERANGE: return "max_neighbors outside 1..ORCA_K_MAX";
-    case ORCA_ENOTSUP: return "not supported by this entry point";
     default: return "unknown status";
     }
 }

@@ -529,8 +529,21 @@ struct ProjLines {
 // minimised last: kDir (v_max times i3's inward normal), kProjDisc (the
 // equal-penetration boundary of a and i3 on the circle), kProjProj (the
 // point of equal penetration of a, b and i3), kTie (v_pref projected onto
-// the boundary of a and i3).
-enum ActiveKind { kFree = 0, kDisc, kLine, kLineLine, kLineDisc, kDir, kProjDisc, kProjProj, kTie };
+// the boundary of a and i3); with acceleration lines, a or b below their
+// count stands for that hard line itself instead of a boundary.  kCentre:
+// the acceleration octagon's centre (LP2 failed on a hard line).
+enum ActiveKind {
+    kFree = 0,
+    kDisc,
+    kLine,
+    kLineLine,
+    kLineDisc,
+    kDir,
+    kProjDisc,
+    kProjProj,
+    kTie,
+    kCentre
+};
 
 struct ActiveSet {
     int kind;
@@ -739,6 +752,12 @@ __device__ __forceinline__ void accel_centre(float vx, float vy, float vmax, flo
     cy = vy * sc;
 }
 
+// Distance of the octagon's edges from its centre, a dt cos(pi/8).
+__device__ __forceinline__ float accel_half_width(float acc, float dt)
+{
+    return acc * dt * 0.92387953f;
+}
+
 template <int BLOCK>
 __device__ __forceinline__ void write_accel_lines(float cx, float cy, float h, float4 *lines,
                                                   int tid)
@@ -855,7 +874,7 @@ __device__ __forceinline__ void step_agent(int s, const GridMeta &g, const Scene
     float cx = 0.0f, cy = 0.0f;
     if (ACC && nh) {
         accel_centre(vxi, vyi, vmax, cx, cy);
-        write_accel_lines<BLOCK>(cx, cy, acc * p.dt * 0.92387953f /* cos(pi/8) */, lines, tid);
+        write_accel_lines<BLOCK>(cx, cy, accel_half_width(acc, p.dt), lines, tid);
     }
     desired_velocity(p, xi, yi, vmax, prx, pry);
 

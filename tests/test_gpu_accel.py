@@ -142,3 +142,73 @@ def test_head_on_vehicle_with_low_cap_brakes_late():
     _print("min clearance without / with cap", res)
     assert res[0.0] > -1e-4
     assert res[1.0] < res[0.0]
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+@pytest.mark.parametrize("accel", [(1.0, 2.0), (2.5, 0.0)])
+def test_capped_step_backward_matches_oracle(accel):
+    """The adjoint through the acceleration lines (q = c + h n_k, c = v or v
+    scaled onto the speed circle) against the oracle's forward-mode
+    gradient, from a state where the caps bind for many agents (crowd
+    accelerating from rest towards its goals)."""
+    import torch
+    from paper_2008_11578_amd import orca
+    sc = scenarios.c5_rollout(seed=6, n=4096, side=120.0)
+    params = dataclasses.replace(sc.params, accel=accel)
+    st = orca.State.from_arrays(sc)
+    nxt = st.clone()
+    ws = orca.Workspace(st.n)
+    for _ in range(6):
+        orca.step(st, params, ws, out=nxt)
+        st, nxt = nxt, st
+    torch.cuda.synchronize()
+    S = st.to_numpy()
+    o_cap = oracle.step(S, params)
+    o_free = oracle.step(S, dataclasses.replace(params, accel=(0.0, 0.0)))
+    bind = np.hypot(o_cap["vx"] - o_free["vx"], o_cap["vy"] - o_free["vy"]) > 1e-4
+    _print("accel", accel, "cap binds for", int(bind.sum()), "of", st.n)
+    assert bind.mean() > 0.1
+    rng = np.random.default_rng(4)
+    cot = [rng.normal(size=st.n).astype(np.float32) for _ in range(4)]
+    g = [torch.as_tensor(c).cuda() for c in cot]
+    gpr = torch.zeros(st.n, device="cuda")
+    gpy = torch.zeros(st.n, device="cuda")
+    gt = torch.zeros(1, device="cuda")
+    out = orca.step_backward(st, params, orca.Workspace(st.n, backward=True), *g, gpr, gpy, gt)
+    torch.cuda.synchronize()
+    gpx, gpy0, gvx, gvy = [t.cpu().numpy() for t in out]
+    o = oracle.step_vjp(S, params, *[c.astype(np.float64) for c in cot])
+    # Agents touching a neighbour (||P| - R| below 1e-4) sit where the velocity
+    # obstacle switches to the overlap form: d leg / d P grows like
+    # 1/sqrt(|P|^2 - R^2), so FP32 and FP64 position cotangents there differ
+    # by whole percents (the oracle's own derivative already departs from its
+    # finite differences).  They are left out of the position check and kept
+    # rare; velocity and pref cotangents are checked for everyone.
+    on = oracle.step(S, params, want_neighbors=True)
+    gap = np.full(st.n, np.inf)
+    for q in range(on["nbr"].shape[1]):
+        j = on["nbr"][:, q]
+        ok = (j >= 0) & (q < on["cnt"])
+        jj = np.where(ok, j, 0)
+        d = np.hypot(S["px"][jj].astype(np.float64) - S["px"], S["py"][jj].astype(np.float64) - S["py"])
+        r = S["radius"].astype(np.float64) + S["radius"][jj]
+        gap = np.where(ok, np.minimum(gap, d - r), gap)
+    touch = np.abs(gap) < 1e-4
+    _print("touching agents", int(touch.sum()))
+    assert touch.mean() < 0.01
+    keep = ~touch
+    for a, k, tol, mask in ((gvx, "g_vx", 1e-4, None), (gvy, "g_vy", 1e-4, None),
+                            (gpr.cpu().numpy(), "g_pref_x", 1e-4, None),
+                            (gpy.cpu().numpy(), "g_pref_y", 1e-4, None),
+                            (gpx, "g_px", 5e-3, keep), (gpy0, "g_py", 5e-3, keep)):
+        if mask is not None:
+            a, ref = a[mask], o[k][mask]
+        else:
+            ref = o[k]
+        _print(k, _rel(a, ref))
+        assert _rel(a, ref) <= tol, (k, _rel(a, ref))
+        assert np.max(np.abs(a - ref)) <= 1e-3 * np.max(np.abs(ref)), k
+    assert abs(float(gt.item()) - o["g_tau"]) <= 1e-4 * abs(o["g_tau"])
