@@ -75,6 +75,24 @@ def traffic_from_profile(kernel_hash: str):
     return float(mb.group(1))
 
 
+def valu_from_profile(kernel_hash: str):
+    """VALU busy and lane utilisation (percent) of the step kernel from the
+    committed rocprofv3 counter summary, or None when missing or taken on
+    other kernel source."""
+    path = os.path.join(ROOT, "profiles", "k_step_c3_1M_valu.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    mh = re.search(r"source_hash:\s*([0-9a-f]+)", txt)
+    mb = re.search(r"valu_busy_pct:\s*([0-9.eE+]+)", txt)
+    mu = re.search(r"valu_utilization_pct:\s*([0-9.eE+]+)", txt)
+    mi = re.search(r"valu_insts_per_launch:\s*([0-9.eE+]+)", txt)
+    if not mh or not mb or not mu or not mi or mh.group(1) != kernel_hash:
+        return None
+    return {"valu_busy_pct": float(mb.group(1)), "valu_utilization_pct": float(mu.group(1)),
+            "valu_insts_per_launch": float(mi.group(1))}
+
+
 class HipEvents:
     """Raw hipEvent_t handles from the HIP runtime torch has loaded."""
 
@@ -422,6 +440,14 @@ def main(argv=None):
                 "hbm_algorithmic_GBs": STEP_BYTES_PER_AGENT * n / (k_ms * 1e-3) / 1e9,
                 "hbm_measured_GBs": (traffic / (k_ms * 1e-3) / 1e9) if traffic else None,
                 "hbm_peak_GBs": HBM_PEAK_GBS, "source_hash": kh}
+        valu = valu_from_profile(kh)
+        if valu:
+            # lane-ops the hardware executed (active lanes of every VALU
+            # instruction) per second, against the same peak
+            executed = (valu["valu_insts_per_launch"] * 64 * valu["valu_utilization_pct"] / 100
+                        / (k_ms * 1e-3) / 1e12)
+            roof.update(valu, executed_lane_ops_Tps=executed,
+                        executed_frac=executed / VALU_PEAK_TOPS)
 
     batched = bench_batched(args.batched_steps) if args.batched_steps > 0 else None
     adjoint = bench_adjoint() if args.adjoint else None
