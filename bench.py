@@ -288,6 +288,105 @@ def bench_vehicle_share(steps: int = 100, warmup: int = 10):
             "rates": rates, "spread": hi / lo - 1.0}
 
 
+def bench_extensions(reps: int = 20):
+    """The rows beyond the plain step, on the dense crossing's 1,048,576
+    agents: leaving at the goal (orca_remove_arrived, a stable compaction,
+    against HBM), entering (orca_spawn with 16,384 candidates), the overlap
+    statistics (orca_overlap_stats) and the step with acceleration caps
+    against the same step without them.  HIP events on the library's
+    stream (torch's current stream) around `reps` calls."""
+    import dataclasses
+    import numpy as np
+    import torch
+    from paper_2008_11578_amd import orca, scenarios
+
+    def timed(fn, k=reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    sc = scenarios.c3_crossing()
+    n = sc.n
+    arr = sc.arrays()
+    # one agent in ten stands on its goal, so removal keeps nine in ten
+    rng = np.random.default_rng(17)
+    done = rng.random(n) < 0.1
+    arr = dict(arr)
+    arr["pref_x"] = np.where(done, arr["px"], arr["pref_x"]).astype(np.float32)
+    arr["pref_y"] = np.where(done, arr["py"], arr["pref_y"]).astype(np.float32)
+    st = orca.State.from_arrays(arr)
+    out = st.clone()
+    o2n = torch.empty(n, dtype=torch.int32, device="cuda")
+    lws = orca.LifecycleWorkspace(n, orca.SPAWN_MAX)
+    kept = int(orca.remove_arrived(st, out, lws, old_to_new=o2n).item())
+    rm_ms = timed(lambda: orca.remove_arrived(st, out, lws, old_to_new=o2n))
+    # read 9 fields (33 B) of every agent, write them for the survivors and
+    # the old-to-new index of every agent
+    rm_bytes = 33 * n + 33 * kept + 4 * n
+    rm = {"ms": rm_ms, "agents": n, "kept": kept, "algorithmic_bytes": rm_bytes,
+          "GBs": rm_bytes / (rm_ms * 1e-3) / 1e9,
+          "hbm_frac": rm_bytes / (rm_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+    # spawning: 16,384 candidates uniform over the square against everyone
+    nc = orca.SPAWN_MAX
+    side = 700.0
+    cand = {k: np.zeros(nc, np.float32) for k in orca.STATE_FIELDS if k != "cls"}
+    cand["px"] = rng.uniform(0, side, nc).astype(np.float32)
+    cand["py"] = rng.uniform(0, side, nc).astype(np.float32)
+    cand["pref_x"] = rng.uniform(0, side, nc).astype(np.float32)
+    cand["pref_y"] = rng.uniform(0, side, nc).astype(np.float32)
+    cand["radius"] = np.full(nc, 0.3, np.float32)
+    cand["max_speed"] = np.full(nc, 1.5, np.float32)
+    cand["cls"] = np.zeros(nc, np.uint8)
+    cst = orca.State.from_arrays(cand)
+    big = orca.State(**{k: torch.cat([getattr(st, k), torch.zeros(nc, dtype=getattr(st, k).dtype,
+                                                                  device="cuda")])
+                        for k in orca.STATE_FIELDS})
+    acc = torch.empty(nc, dtype=torch.uint8, device="cuda")
+    tot = int(orca.spawn(big, n, cst, 1.0, lws, accepted=acc).item())
+    sp_ms = timed(lambda: orca.spawn(big, n, cst, 1.0, lws, accepted=acc))
+    sp = {"ms": sp_ms, "agents": n, "candidates": nc, "accepted": tot - n,
+          "candidates_per_s": nc / (sp_ms * 1e-3)}
+
+    # overlap statistics over pairs closer than 1 m (twice the largest radius)
+    ows = orca.OverlapWorkspace(n)
+    ores = orca.overlap_stats(st, 1.0, ows).cpu().numpy()
+    ov_ms = timed(lambda: orca.overlap_stats(st, 1.0, ows))
+    ov = {"ms": ov_ms, "agents": n, "reach": 1.0, "pairs": int(ores[0]),
+          "agents_per_s": n / (ov_ms * 1e-3)}
+
+    # the dense crossing's step with acceleration caps (2 m/s^2 for everyone)
+    params = dataclasses.replace(sc.params, cell_size=0.6)
+    capped = dataclasses.replace(params, accel=(2.0, 2.0))
+    res = {}
+    for name, p in (("uncapped", params), ("capped", capped)):
+        a = orca.State.from_arrays(sc)
+        b = a.clone()
+        ws = orca.Workspace(n)
+        for _ in range(5):
+            orca.step(a, p, ws, out=b)
+            a, b = b, a
+
+        def two():
+            orca.step(a, p, ws, out=b)
+            orca.step(b, p, ws, out=a)
+
+        res[name] = timed(two, k=10) / 2
+    ac = {"ms_per_step_capped": res["capped"], "ms_per_step_uncapped": res["uncapped"],
+          "agent_steps_per_s_capped": n / (res["capped"] * 1e-3),
+          "ratio": res["capped"] / res["uncapped"]}
+    log(f"[bench] extensions: remove {rm_ms:.3f} ms ({rm['GBs']:.0f} GB/s), spawn {sp_ms:.3f} ms, "
+        f"overlap {ov_ms:.3f} ms, capped step {res['capped']:.3f} ms vs {res['uncapped']:.3f}")
+    return {"metric": "ms per call on the 1,048,576-agent dense crossing",
+            "remove_arrived": rm, "spawn": sp, "overlap_stats": ov, "accel_step": ac}
+
+
 def bench_adjoint(reps: int = 3):
     """Differentiable rollout: 16,384 agents, 50 steps, checkpoints every 10:
     forward rollout, then the backward pass (segment replays and
@@ -346,6 +445,8 @@ def main(argv=None):
                     help="graph-captured steps of the 512-scene batched form (0 skips it)")
     ap.add_argument("--no-adjoint", dest="adjoint", action="store_false",
                     help="skip the differentiable-rollout leg")
+    ap.add_argument("--no-extensions", dest="extensions", action="store_false",
+                    help="skip the lifecycle / overlap / acceleration-cap leg")
     ap.add_argument("--no-vehicle-share", dest="vehicle_share", action="store_false",
                     help="skip the vehicle-share sweep of the mixed crowd")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -452,6 +553,7 @@ def main(argv=None):
     batched = bench_batched(args.batched_steps) if args.batched_steps > 0 else None
     adjoint = bench_adjoint() if args.adjoint else None
     vshare = bench_vehicle_share() if args.vehicle_share else None
+    ext = bench_extensions() if args.extensions else None
 
     out = {
         "metric": "agent-steps/sec at 1M agents (ORCA+LP); batched & adjoint steps/sec",
@@ -476,6 +578,7 @@ def main(argv=None):
         "batched": batched,
         "adjoint": adjoint,
         "vehicle_share": vshare,
+        "extensions": ext,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -213,10 +213,12 @@ __global__ __launch_bounds__(kBlock) void k_spawn_check(orca_agents_in cand, int
                                                          const float4 *__restrict__ s0,
                                                          const float *__restrict__ bounds,
                                                          float t_clear, int n,
-                                                         uint8_t *__restrict__ blocked)
+                                                         uint8_t *__restrict__ blocked,
+                                                         int32_t *__restrict__ conf_count)
 {
     const int c = blockIdx.x * kBlock + threadIdx.x;
     if (c >= nc) return;
+    conf_count[c] = 0;
     const float cx = cand.px[c], cy = cand.py[c], cr = cand.radius[c], cs = cand.max_speed[c];
     const double t = (double)t_clear;
     bool hit = false;
@@ -236,14 +238,28 @@ __global__ __launch_bounds__(kBlock) void k_spawn_check(orca_agents_in cand, int
 }
 
 // (entering 3) each candidate's earlier conflicting candidates, found by
-// tiles of candidates staged in LDS.
+// tiles of candidates staged in LDS.  A candidate blocked by the agents is
+// rejected whatever else happens, so lists are built for the unblocked ones
+// and hold unblocked candidates only.  blockIdx.y splits the earlier
+// candidates into chunks of kPairChunk tiles, so a list is filled through
+// its atomic counter (zeroed by k_spawn_check); the decision rounds read a
+// list as a set, and one that overflows sends its candidate to the
+// exhaustive test, so the order of the entries does not matter.
+constexpr int kPairChunk = 8;
+
 __global__ __launch_bounds__(kBlock) void k_spawn_pairs(orca_agents_in cand, int nc, float t_clear,
+                                                         const uint8_t *__restrict__ blocked,
                                                          int32_t *__restrict__ conf_count,
                                                          int32_t *__restrict__ conf)
 {
     __shared__ float4 tile[kBlock];
+    __shared__ uint8_t tile_blocked[kBlock];
+    const int last = min((int)(blockIdx.x + 1) * kBlock, nc);  // candidates before the block's end
+    const int b0 = (int)blockIdx.y * kPairChunk * kBlock;
+    if (b0 >= last) return;  // the whole workgroup: no earlier candidates in this chunk
+    const int b1 = min(b0 + kPairChunk * kBlock, last);
     const int c = blockIdx.x * kBlock + threadIdx.x;
-    const bool live = c < nc;
+    const bool live = c < nc && !blocked[c];
     float cx = 0.0f, cy = 0.0f, cr = 0.0f, cs = 0.0f;
     if (live) {
         cx = cand.px[c];
@@ -252,26 +268,26 @@ __global__ __launch_bounds__(kBlock) void k_spawn_pairs(orca_agents_in cand, int
         cs = cand.max_speed[c];
     }
     const double t = (double)t_clear;
-    int cnt = 0;
-    const int last = min((int)(blockIdx.x + 1) * kBlock, nc);  // candidates before the block's end
-    for (int base = 0; base < last; base += kBlock) {
+    for (int base = b0; base < b1; base += kBlock) {
         const int e0 = base + threadIdx.x;
         __syncthreads();
-        if (e0 < nc)
+        if (e0 < nc) {
             tile[threadIdx.x] = make_float4(cand.px[e0], cand.py[e0], cand.radius[e0],
                                             cand.max_speed[e0]);
+            tile_blocked[threadIdx.x] = blocked[e0];
+        }
         __syncthreads();
         if (!live) continue;
         const int m = min(kBlock, c - base);  // earlier candidates only
         for (int k = 0; k < m; ++k) {
+            if (tile_blocked[k]) continue;
             const float4 e = tile[k];
             if (too_close(cx, cy, cr, cs, e.x, e.y, e.z, e.w, t)) {
-                if (cnt < kConfCap) conf[(int64_t)c * kConfCap + cnt] = base + k;
-                ++cnt;
+                const int slot = atomicAdd(&conf_count[c], 1);
+                if (slot < kConfCap) conf[(int64_t)c * kConfCap + slot] = base + k;
             }
         }
     }
-    if (live) conf_count[c] = cnt;
 }
 
 // (entering 4) one workgroup: first-come decisions in rounds, then the
@@ -498,9 +514,10 @@ hipError_t launch_spawn(const orca_agents_buf &state, int n, const orca_agents_i
     if (ncb > 0) {
         hipLaunchKernelGGL(k_spawn_check, dim3(ncb), dim3(kBlock), 0, stream, cand, n_cand,
                            (const float *)state.max_speed, w.meta, w.start, w.s0, b.bounds,
-                           t_clear, n, b.blocked);
-        hipLaunchKernelGGL(k_spawn_pairs, dim3(ncb), dim3(kBlock), 0, stream, cand, n_cand,
-                           t_clear, b.conf_count, b.conf);
+                           t_clear, n, b.blocked, b.conf_count);
+        const int chunks = (ncb + kPairChunk - 1) / kPairChunk;
+        hipLaunchKernelGGL(k_spawn_pairs, dim3(ncb, chunks), dim3(kBlock), 0, stream, cand,
+                           n_cand, t_clear, b.blocked, b.conf_count, b.conf);
     }
     hipLaunchKernelGGL(k_spawn_resolve, dim3(1), dim3(kScanThreads), 0, stream, cand, n_cand,
                        t_clear, b.blocked, b.conf_count, b.conf, state, n, n_total, accepted);
