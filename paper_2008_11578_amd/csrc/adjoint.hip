@@ -193,12 +193,9 @@ __device__ __forceinline__ void adjoint_agent(int s, const AdjArgs &a, const Gri
     const float acc = ACC ? (ci ? p.acc1 : p.acc0) : 0.0f;
     const int nh = (ACC && acc > 0.0f) ? dev::kHard : 0;
     dev::build_halfplanes<K, BLOCK>(pos, m, a.s0, a.s1, xi, yi, vxi, vyi, ri, i, ci, p, lines,
-                                    tid, nh);
+                                    tid);
     float cx = 0.0f, cy = 0.0f;
-    if (ACC && nh) {
-        dev::accel_centre(vxi, vyi, vmax, cx, cy);
-        dev::write_accel_lines<BLOCK>(cx, cy, dev::accel_half_width(acc, p.dt), lines, tid);
-    }
+    if (ACC && nh) dev::accel_centre(vxi, vyi, vmax, cx, cy);
     const float pin_x = a.in.pref_x[i], pin_y = a.in.pref_y[i];
     float prx = pin_x, pry = pin_y;
     dev::desired_velocity(p, xi, yi, vmax, prx, pry);
@@ -210,7 +207,8 @@ __device__ __forceinline__ void adjoint_agent(int s, const AdjArgs &a, const Gri
         d2g = gxg * gxg + gyg * gyg;
         scg = d2g > 0.0f ? fminf(vmax / sqrtf(d2g), p.inv_dt) : 0.0f;
     }
-    dev::LdsLines<BLOCK> src{lines, tid};
+    const dev::LdsLines<BLOCK, ACC> src{lines, tid, nh, cx, cy,
+                                        ACC && nh ? dev::accel_half_width(acc, p.dt) : 0.0f};
     float vx, vy;
     dev::ActiveSet rec{dev::kFree, -1, -1, -1};
     const int mt = nh + m;
@@ -222,7 +220,7 @@ __device__ __forceinline__ void adjoint_agent(int s, const AdjArgs &a, const Gri
         rec.kind = dev::kCentre;
     }
     if (fail < mt)
-        dev::lp3<true, BLOCK, ACC>(lines, tid, mt, nh, fail, vmax, prx, pry, p.eps, vx, vy, &rec);
+        dev::lp3<true, BLOCK, ACC>(src, mt, fail, vmax, prx, pry, p.eps, vx, vy, &rec);
 
     // -- cotangent of the new velocity: v' directly and through p' = p + v' dt --
     const float gpx = a.gpx1[i], gpy = a.gpy1[i];
@@ -237,7 +235,7 @@ __device__ __forceinline__ void adjoint_agent(int s, const AdjArgs &a, const Gri
     }
     float pbx = 0.0f, pby = 0.0f;  // cotangent of the desired velocity
     float cbx = 0.0f, cby = 0.0f;  // cotangent of the acceleration octagon's centre
-    auto Lq = [&](int idx) { return lines[idx * BLOCK + tid]; };
+    auto Lq = [&](int idx) { return src.line(idx); };
     // Rows of an LP3 sub-problem: line j < nh is a hard line, g = n_j,
     // r = n_j . q_j; otherwise the equal-penetration boundary of j and i3,
     // g = n_i3 - n_j, r = n_i3 . q_i3 - n_j . q_j.  For v = G^-1 r the
@@ -450,7 +448,7 @@ __device__ __forceinline__ void adjoint_agent(int s, const AdjArgs &a, const Gri
 template <int K, int BLOCK, bool ACC>
 __global__ __launch_bounds__(BLOCK) void k_adjoint(AdjArgs a)
 {
-    __shared__ float4 lines[dev::StepShape<K, ACC>::kSlots * BLOCK];
+    __shared__ float4 lines[dev::KnnShape<K>::kSlots * BLOCK];
     const int tid = threadIdx.x;
     const int s = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + tid;
     if (s >= a.n) return;

@@ -166,7 +166,7 @@ __device__ __forceinline__ void batch_agent(const BatchArgs &a, int s, float4 *l
 template <int K, int BLOCK, bool ACC>
 __global__ __launch_bounds__(BLOCK) void k_step_batched(BatchArgs a)
 {
-    __shared__ float4 lines[dev::StepShape<K, ACC>::kSlots * BLOCK];
+    __shared__ float4 lines[dev::KnnShape<K>::kSlots * BLOCK];
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int n_tiles = (a.n + kTile - 1) / kTile;
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(BLOCK) void k_step_batched(BatchArgs a)
 template <int K, int BLOCK, bool ACC>
 __global__ __launch_bounds__(BLOCK) void k_step_batched_flat(BatchArgs a)
 {
-    __shared__ float4 lines[dev::StepShape<K, ACC>::kSlots * BLOCK];
+    __shared__ float4 lines[dev::KnnShape<K>::kSlots * BLOCK];
     const int tid = threadIdx.x;
     const int s = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + tid;
     if (s < a.n) batch_agent<K, BLOCK, ACC>(a, s, lines, tid);

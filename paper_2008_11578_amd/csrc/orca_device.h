@@ -76,16 +76,8 @@ struct KnnShape {
     static constexpr int kCap = 2 * kSlots;       // buffer entries per lane
 };
 
-// Acceleration lines of an acceleration-limited agent (see accel_lines).
+// Acceleration lines of an acceleration-limited agent (see accel_line).
 constexpr int kHard = 8;
-
-// LDS slots per lane of the step: the neighbour buffer, then the half-planes
-// (with ACC, up to kHard acceleration lines ahead of the K ORCA lines).
-template <int K, bool ACC>
-struct StepShape {
-    static constexpr int kLines = ACC ? K + kHard : K;
-    static constexpr int kSlots = KnnShape<K>::kSlots > kLines ? KnnShape<K>::kSlots : kLines;
-};
 
 // Entry e of lane `tid` inside a [slot][BLOCK] float4 array viewed as u64.
 template <int BLOCK>
@@ -472,14 +464,69 @@ __device__ __forceinline__ float4 halfplane(float pax, float pay, float vax, flo
     return make_float4(vax + f * ux, vay + f * uy, ny, -nx);
 }
 
-// Half-planes of this lane, stored in LDS column `tid`.
-template <int BLOCK>
+// Acceleration limit (Sec. 5: acceleration-limited vehicles add linear
+// constraints of their own motion to the same LP).  Within one step the
+// velocity may change by at most a dt: the new velocity must lie in the
+// regular octagon inscribed in the disc of radius a dt about c, the current
+// velocity scaled onto the speed circle when it lies outside it (so the
+// octagon and the speed disc always meet).  Edge k has outward normal n_k at
+// angle k pi/4 at distance h = a dt cos(pi/8) from c; as a line,
+// q = c + h n_k, d = (-n_k.y, n_k.x).  The lines are hard constraints: they
+// precede the ORCA lines in LP2 and LP3 never relaxes them.
+__device__ __forceinline__ void accel_centre(float vx, float vy, float vmax, float &cx, float &cy)
+{
+    const float v2 = vx * vx + vy * vy;
+    const float sc = v2 > vmax * vmax ? vmax / sqrtf(v2) : 1.0f;
+    cx = vx * sc;
+    cy = vy * sc;
+}
+
+// Distance of the octagon's edges from its centre, a dt cos(pi/8).
+__device__ __forceinline__ float accel_half_width(float acc, float dt)
+{
+    return acc * dt * 0.92387953f;
+}
+
+// cos(k pi/4) for k in 0..7, exactly 0, +-1 or +-0.70710678f.
+__device__ __forceinline__ float cos_quarter(int k)
+{
+    const int m = k & 7;
+    const float mag = (m & 1) ? 0.70710678f : ((m & 2) ? 0.0f : 1.0f);
+    return (m >= 3 && m <= 5) ? -mag : mag;
+}
+
+// Acceleration line k, generated where it is read (no LDS): q = c + h n_k
+// with single-rounding fmaf, so every read of a line gives the same bits.
+__device__ __forceinline__ float4 accel_line(int k, float cx, float cy, float h)
+{
+    const float nx = cos_quarter(k), ny = cos_quarter(k + 6);  // sin(x) = cos(x - pi/2)
+    return make_float4(fmaf(h, nx, cx), fmaf(h, ny, cy), -ny, nx);
+}
+
+// The lines of this lane's LP: with ACC the first nh are its acceleration
+// lines (generated from the centre (cx, cy) and half-width h), then the
+// half-planes, stored in LDS column `tid`.
+template <int BLOCK, bool ACC = false>
 struct LdsLines {
     const float4 *L;
     int tid;
+    int nh = 0;
+    float cx = 0.0f, cy = 0.0f, h = 0.0f;
+    __device__ __forceinline__ float4 line(int j) const
+    {
+        if (!ACC) return L[j * BLOCK + tid];
+        // a select, not a branch: the LP code around keeps the control flow
+        // (and so the multiply-add fusion) of the kernel without caps, and an
+        // agent without a cap gets the same bits from both kernels
+        const float4 s = L[(j >= nh ? j - nh : 0) * BLOCK + tid];
+        const float4 a = accel_line(j, cx, cy, h);
+        const bool hard = j < nh;
+        return make_float4(hard ? a.x : s.x, hard ? a.y : s.y, hard ? a.z : s.z,
+                           hard ? a.w : s.w);
+    }
     __device__ __forceinline__ bool get(int j, float4 &l) const
     {
-        l = L[j * BLOCK + tid];
+        l = line(j);
         return true;
     }
 };
@@ -497,16 +544,14 @@ struct LdsLines {
 // away from the speed disc.
 template <int BLOCK, bool ACC = false>
 struct ProjLines {
-    const float4 *L;
-    int tid;
+    const LdsLines<BLOCK, ACC> &ls;
     float4 li;
     float ci;    // det(d_i, q_i)
     float eps;
-    int nh;
     __device__ __forceinline__ bool get(int j, float4 &out) const
     {
-        const float4 lj = L[j * BLOCK + tid];
-        if (ACC && j < nh) {
+        const float4 lj = ls.line(j);
+        if (ACC && j < ls.nh) {
             out = lj;
             return true;
         }
@@ -680,17 +725,17 @@ __device__ __forceinline__ int lp2(const Src &src, int m, float vmax, int mode, 
 // i's permitted side as possible.  With ACC the first nh lines are hard: never
 // relaxed, they bound every re-solve as they are.
 template <bool REC, int BLOCK, bool ACC = false>
-__device__ __forceinline__ void lp3(const float4 *L, int tid, int m, int nh, int fail,
-                                    float vmax, float tx, float ty, float eps, float &vx,
-                                    float &vy, ActiveSet *rec)
+__device__ __forceinline__ void lp3(const LdsLines<BLOCK, ACC> &ls, int m, int fail, float vmax,
+                                    float tx, float ty, float eps, float &vx, float &vy,
+                                    ActiveSet *rec)
 {
     float level = 0.0f;
     float x = vx, y = vy;
-    const int nhard = ACC ? nh : 0;
+    const int nhard = ACC ? ls.nh : 0;
     for (int i = fail > nhard ? fail : nhard; i < m; ++i) {
-        const float4 li = L[i * BLOCK + tid];
+        const float4 li = ls.line(i);
         if (det2(li.z, li.w, li.x - x, li.y - y) <= level) continue;
-        ProjLines<BLOCK, ACC> src{L, tid, li, det2(li.z, li.w, li.x, li.y), eps, nhard};
+        ProjLines<BLOCK, ACC> src{ls, li, det2(li.z, li.w, li.x, li.y), eps};
         float nx = x, ny = y;
         ActiveSet inner;
         if (lp2<REC>(src, i, vmax, 1, -li.w, li.z, tx, ty, eps, nx, ny, &inner) == i) {
@@ -735,41 +780,6 @@ __device__ __host__ __forceinline__ SceneP scene_params(const orca_params &p)
     return s;
 }
 
-// Acceleration limit (Sec. 5: acceleration-limited vehicles add linear
-// constraints of their own motion to the same LP).  Within one step the
-// velocity may change by at most a dt: the new velocity must lie in the
-// regular octagon inscribed in the disc of radius a dt about c, the current
-// velocity scaled onto the speed circle when it lies outside it (so the
-// octagon and the speed disc always meet).  Edge k has outward normal n_k at
-// angle k pi/4 at distance h = a dt cos(pi/8) from c; as a line,
-// q = c + h n_k, d = (-n_k.y, n_k.x).  The lines are hard constraints: they
-// precede the ORCA lines in LP2 and LP3 never relaxes them.
-__device__ __forceinline__ void accel_centre(float vx, float vy, float vmax, float &cx, float &cy)
-{
-    const float v2 = vx * vx + vy * vy;
-    const float sc = v2 > vmax * vmax ? vmax / sqrtf(v2) : 1.0f;
-    cx = vx * sc;
-    cy = vy * sc;
-}
-
-// Distance of the octagon's edges from its centre, a dt cos(pi/8).
-__device__ __forceinline__ float accel_half_width(float acc, float dt)
-{
-    return acc * dt * 0.92387953f;
-}
-
-template <int BLOCK>
-__device__ __forceinline__ void write_accel_lines(float cx, float cy, float h, float4 *lines,
-                                                  int tid)
-{
-    constexpr float kS = 0.70710678f;  // cos(pi/4)
-    constexpr float kNx[kHard] = {1.0f, kS, 0.0f, -kS, -1.0f, -kS, 0.0f, kS};
-    constexpr float kNy[kHard] = {0.0f, kS, 1.0f, kS, 0.0f, -kS, -1.0f, -kS};
-#pragma unroll
-    for (int k = 0; k < kHard; ++k)
-        lines[k * BLOCK + tid] = make_float4(cx + h * kNx[k], cy + h * kNy[k], -kNy[k], kNx[k]);
-}
-
 // The half-planes of the agent's m neighbours into its LDS column.
 // Neighbour states are loaded a group at a time without a branch (unused
 // slots read position 0, a valid entry) so the loads of a group are in
@@ -779,8 +789,7 @@ __device__ __forceinline__ void build_halfplanes(const uint32_t (&pos)[K], int m
                                                  const float4 *__restrict__ s0,
                                                  const float4 *__restrict__ s1, float xi,
                                                  float yi, float vxi, float vyi, float ri, int i,
-                                                 int ci, const SceneP &p, float4 *lines, int tid,
-                                                 int base = 0)
+                                                 int ci, const SceneP &p, float4 *lines, int tid)
 {
     const float fa = ci ? p.f10 : p.f00;  // f[ci][0]
     const float fb = ci ? p.f11 : p.f01;  // f[ci][1]
@@ -800,7 +809,7 @@ __device__ __forceinline__ void build_halfplanes(const uint32_t (&pos)[K], int m
             const int q = q0 + u;
             if (q < K && q < m) {
                 const float f = (__float_as_int(b1[u].z) & 1) ? fb : fa;
-                lines[(base + q) * BLOCK + tid] =
+                lines[q * BLOCK + tid] =
                     halfplane(xi, yi, vxi, vyi, ri, b0[u].x, b0[u].y, b1[u].x, b1[u].y, b0[u].w,
                               f, p.inv_tau, p.inv_dt, i < __float_as_int(b0[u].z));
             }
@@ -824,8 +833,8 @@ __device__ __forceinline__ void desired_velocity(const SceneP &p, float xi, floa
 
 // One whole ORCA step of the agent at cell-order position s: neighbours,
 // half-planes (into the lane's LDS column), LP2, LP3 if needed, update.
-// `lines` is a [StepShape<K, ACC>::kSlots][BLOCK] float4 array; lane `tid`
-// owns column tid.  `guess` (caller order, nullable) keeps each agent's K-th
+// `lines` is a [KnnShape<K>::kSlots][BLOCK] float4 array; lane `tid` owns
+// column tid.  `guess` (caller order, nullable) keeps each agent's K-th
 // neighbour distance between steps (0: none); it only narrows the counting
 // pass.  ACC compiles the acceleration lines in (used for agents whose class
 // has a cap).
@@ -870,15 +879,13 @@ __device__ __forceinline__ void step_agent(int s, const GridMeta &g, const Scene
     float prx = in.pref_x[i], pry = in.pref_y[i];
     const float acc = ACC ? (ci ? p.acc1 : p.acc0) : 0.0f;
     const int nh = (ACC && acc > 0.0f) ? kHard : 0;
-    build_halfplanes<K, BLOCK>(pos, m, s0, s1, xi, yi, vxi, vyi, ri, i, ci, p, lines, tid, nh);
+    build_halfplanes<K, BLOCK>(pos, m, s0, s1, xi, yi, vxi, vyi, ri, i, ci, p, lines, tid);
     float cx = 0.0f, cy = 0.0f;
-    if (ACC && nh) {
-        accel_centre(vxi, vyi, vmax, cx, cy);
-        write_accel_lines<BLOCK>(cx, cy, accel_half_width(acc, p.dt), lines, tid);
-    }
+    if (ACC && nh) accel_centre(vxi, vyi, vmax, cx, cy);
     desired_velocity(p, xi, yi, vmax, prx, pry);
 
-    LdsLines<BLOCK> src{lines, tid};
+    const LdsLines<BLOCK, ACC> src{lines, tid, nh, cx, cy,
+                                   ACC && nh ? accel_half_width(acc, p.dt) : 0.0f};
     const int mt = nh + m;
     float vx, vy;
     int fail = lp2<false>(src, mt, vmax, 0, prx, pry, 0.0f, 0.0f, p.eps, vx, vy, nullptr);
@@ -892,7 +899,7 @@ __device__ __forceinline__ void step_agent(int s, const GridMeta &g, const Scene
         st = 1;
     }
     if (fail < mt) {
-        lp3<false, BLOCK, ACC>(lines, tid, mt, nh, fail, vmax, prx, pry, p.eps, vx, vy, nullptr);
+        lp3<false, BLOCK, ACC>(src, mt, fail, vmax, prx, pry, p.eps, vx, vy, nullptr);
         st = 1;
     }
     out.vx[i] = vx;

@@ -31,7 +31,7 @@ using dev::knn_select;
 template <int K, int BLOCK, bool ACC>
 __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, dev::SceneP p)
 {
-    __shared__ float4 lines[dev::StepShape<K, ACC>::kSlots * BLOCK];
+    __shared__ float4 lines[dev::KnnShape<K>::kSlots * BLOCK];
     const int tid = threadIdx.x;
     const int s = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + tid;
     if (s >= a.n) return;

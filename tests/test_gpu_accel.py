@@ -55,12 +55,19 @@ def test_capped_step_every_velocity_within_its_octagon():
 
 
 def test_cap_too_large_to_bind_equals_uncapped():
+    """Same LP decisions and velocities as without caps.  (The two kernels
+    run the same arithmetic but are separate instantiations whose
+    multiply-adds the compiler may fuse differently, so agreement is to a
+    few FP32 ulps rather than bit for bit; the oracle pins the exact
+    equality.)"""
     sc = _crowd(5000, 60.0, seed=7, veh_share=0.1, accel=(0.0, 0.0))
     st = as_dict(sc)
     g0 = gpu_step(st, sc.params)
     g1 = gpu_step(st, dataclasses.replace(sc.params, accel=(1e6, 1e6)))
-    for k in ("vx", "vy", "px", "py", "status"):
-        np.testing.assert_array_equal(g0[k], g1[k])
+    np.testing.assert_array_equal(g0["status"], g1["status"])
+    dv = np.hypot(g0["vx"] - g1["vx"], g0["vy"] - g1["vy"])
+    _print("max |dv| huge cap vs none", float(dv.max()), "differing", int((dv > 0).sum()))
+    assert dv.max() <= 1e-5
 
 
 def test_uncapped_class_unchanged_by_other_class_cap():
@@ -69,9 +76,12 @@ def test_uncapped_class_unchanged_by_other_class_cap():
     g0 = gpu_step(st, sc.params)
     g1 = gpu_step(st, dataclasses.replace(sc.params, accel=(0.0, 2.0)))
     ped = st["cls"] == 0
-    for k in ("vx", "vy"):
-        np.testing.assert_array_equal(g0[k][ped], g1[k][ped])
-    assert not np.array_equal(g0["vx"][~ped], g1["vx"][~ped])
+    # pedestrians take no acceleration lines: same decisions, velocities to a
+    # few ulps (separate kernel instantiations, see above)
+    np.testing.assert_array_equal(g0["status"][ped], g1["status"][ped])
+    dv = np.hypot(g0["vx"] - g1["vx"], g0["vy"] - g1["vy"])
+    assert dv[ped].max() <= 1e-5
+    assert dv[~ped].max() > 1e-3
 
 
 @pytest.mark.parametrize("mode", [0, 1])
