@@ -447,20 +447,24 @@ __device__ __forceinline__ float4 halfplane(float pax, float pay, float vax, flo
     const float anx = wz ? (a_first ? 1.0f : -1.0f) : wx * iwl;
     const float any = wz ? 0.0f : wy * iwl;
     const float ul = R * it - wl;
-    // leg form
-    const float leg = sqrtf(fmaxf(dist2 - R2, 0.0f));
-    const float id2 = overlap ? 0.0f : 1.0f / dist2;
-    const bool left = det2(Px, Py, wx, wy) > 0.0f;
-    const float sR = left ? R : -R;
-    const float ex = (Px * leg - Py * sR) * id2;
-    const float ey = (Px * sR + Py * leg) * id2;
-    const float lnx = left ? -ey : ey;
-    const float lny = left ? ex : -ex;
-    const float s = Vx * ex + Vy * ey;
-    const float nx = arc ? anx : lnx;
-    const float ny = arc ? any : lny;
-    const float ux = arc ? ul * anx : s * ex - Vx;
-    const float uy = arc ? ul * any : s * ey - Vy;
+    float nx = anx, ny = any, ux = ul * anx, uy = ul * any;
+    // leg form, only where a lane of the wavefront needs it (in dense flows
+    // most half-planes take the cutoff arc: relative velocities are small)
+    if (__any(!arc)) {
+        const float leg = sqrtf(fmaxf(dist2 - R2, 0.0f));
+        const float id2 = overlap ? 0.0f : 1.0f / dist2;
+        const bool left = det2(Px, Py, wx, wy) > 0.0f;
+        const float sR = left ? R : -R;
+        const float ex = (Px * leg - Py * sR) * id2;
+        const float ey = (Px * sR + Py * leg) * id2;
+        const float lnx = left ? -ey : ey;
+        const float lny = left ? ex : -ex;
+        const float s = Vx * ex + Vy * ey;
+        nx = arc ? nx : lnx;
+        ny = arc ? ny : lny;
+        ux = arc ? ux : s * ex - Vx;
+        uy = arc ? uy : s * ey - Vy;
+    }
     return make_float4(vax + f * ux, vay + f * uy, ny, -nx);
 }
 
