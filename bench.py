@@ -457,7 +457,8 @@ def main(argv=None):
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} (WORLD_SIZE={world}) is not "
-              "supported: the ORCA step has no multi-GPU path in this build", file=sys.stderr)
+              "supported: the library steps a scene on one GPU (sharding by scenes or by spatial "
+              "slabs is a design, not an implemented path)", file=sys.stderr)
         return 2
 
     import numpy as np
