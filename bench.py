@@ -387,6 +387,37 @@ def bench_extensions(reps: int = 20):
             "remove_arrived": rm, "spawn": sp, "overlap_stats": ov, "accel_step": ac}
 
 
+def bench_crossing():
+    """The paper's first experiment shape run end to end: two-way and
+    four-way crossings of 2,500 agents per group in a 100 m square with
+    spawning at clear points, stepping, overlap statistics and removal at the
+    goal every step, until everyone has arrived.  Reports the wall time per
+    step (host synchronisation included), the agent-steps/s this gives, the
+    flow of arrivals, the LP3 share and the overlaps."""
+    import torch
+    from paper_2008_11578_amd import crossing
+    out = {}
+    for kind in ("2way", "4way"):
+        cfg = crossing.CrossingConfig(kind=kind, per_group=2500, side=100.0, strip=10.0,
+                                      proposals=64, t_clear=1.0, max_steps=5000, seed=11)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = crossing.run(cfg, record=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        dt = float(cfg.params.dt)
+        out[kind] = {"agents": r["spawned"], "arrived": r["arrived"], "steps": r["steps"],
+                     "agent_steps": r["agent_steps"], "wall_s": el,
+                     "ms_per_step": el / max(r["steps"], 1) * 1e3,
+                     "agent_steps_per_s": r["agent_steps"] / el,
+                     "arrivals_per_sim_s": r["arrived"] / (r["steps"] * dt),
+                     "lp3_share": r["lp3_share"], "max_overlap_pairs": r["max_overlap_pairs"],
+                     "min_clearance_m": r["min_clearance"]}
+        log(f"[bench] crossing {kind}: {r['spawned']} agents, {r['steps']} steps in {el:.2f} s, "
+            f"lp3 {r['lp3_share']:.3f}, max overlap pairs {r['max_overlap_pairs']}")
+    return {"metric": "crossings with spawning and removal, 2,500 agents per group", **out}
+
+
 def bench_adjoint(reps: int = 3):
     """Differentiable rollout: 16,384 agents, 50 steps, checkpoints every 10:
     forward rollout, then the backward pass (segment replays and
@@ -445,6 +476,8 @@ def main(argv=None):
                     help="graph-captured steps of the 512-scene batched form (0 skips it)")
     ap.add_argument("--no-adjoint", dest="adjoint", action="store_false",
                     help="skip the differentiable-rollout leg")
+    ap.add_argument("--no-crossing", dest="crossing", action="store_false",
+                    help="skip the crossing runs with spawning and removal")
     ap.add_argument("--no-extensions", dest="extensions", action="store_false",
                     help="skip the lifecycle / overlap / acceleration-cap leg")
     ap.add_argument("--no-vehicle-share", dest="vehicle_share", action="store_false",
@@ -555,6 +588,7 @@ def main(argv=None):
     adjoint = bench_adjoint() if args.adjoint else None
     vshare = bench_vehicle_share() if args.vehicle_share else None
     ext = bench_extensions() if args.extensions else None
+    cross = bench_crossing() if args.crossing else None
 
     out = {
         "metric": "agent-steps/sec at 1M agents (ORCA+LP); batched & adjoint steps/sec",
@@ -580,6 +614,7 @@ def main(argv=None):
         "adjoint": adjoint,
         "vehicle_share": vshare,
         "extensions": ext,
+        "crossing": cross,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -97,6 +97,7 @@ def run(cfg: CrossingConfig, record: bool = True) -> Dict[str, object]:
     rows: List[dict] = []
     lp3_steps = 0.0
     agent_steps = 0
+    pending = None  # (accepted flags, owners) of the last spawn, read with the step's results
     for t in range(cfg.max_steps):
         # spawn: every group still owing agents proposes candidates
         props, owner = [], []
@@ -110,27 +111,40 @@ def run(cfg: CrossingConfig, record: bool = True) -> Dict[str, object]:
             cand = orca.State.from_arrays(cand_np)
             acc = torch.empty(cand.n, dtype=torch.uint8, device="cuda")
             tot = orca.spawn(a, n, cand, cfg.t_clear, life_ws, accepted=acc)
-            acc_h = acc.cpu().numpy().astype(bool)
-            own = np.concatenate(owner)
+            n = int(tot.item())  # the one synchronisation before the step
+            pending = (acc, np.concatenate(owner))
+        else:
+            pending = None
+        if n == 0 and not any(q > 0 for q in quota):
+            break
+        # one ORCA step of everyone present, in place, then the statistics,
+        # the removal and the spawn decisions, all read back in one copy
+        cur = _view(a, n)
+        parts = []
+        if n > 0:
+            orca.step(cur, cfg.params, step_ws, out=cur, status=status[:n])
+            parts.append(orca.overlap_stats(cur, reach, ov_ws))
+            parts.append(status[:n].sum(dtype=torch.float64).reshape(1))
+            parts.append(orca.remove_arrived(cur, _view(b, n), life_ws).to(torch.float64))
+        if pending is not None:
+            parts.append(pending[0].to(torch.float64))
+        packed = torch.cat(parts).cpu().numpy() if parts else np.zeros(0)
+        if n > 0:
+            stats, lp3_n, left = packed[:3], float(packed[3]), int(packed[4])
+            lp3 = lp3_n / n
+            lp3_steps += lp3_n
+            agent_steps += n
+            rest = packed[5:]
+        else:
+            stats = np.array([0.0, 0.0, np.inf])
+            lp3, left = 0.0, 0
+            rest = packed
+        if pending is not None:
+            acc_h = rest.astype(bool)
+            own = pending[1]
             for g in range(G):
                 quota[g] -= int(acc_h[own == g].sum())
             spawned += int(acc_h.sum())
-            n = int(tot.item())
-        if n == 0 and not any(q > 0 for q in quota):
-            break
-        # one ORCA step of everyone present, in place
-        cur = _view(a, n)
-        if n > 0:
-            orca.step(cur, cfg.params, step_ws, out=cur, status=status[:n])
-            stats = orca.overlap_stats(cur, reach, ov_ws).cpu().numpy()
-            lp3 = float(status[:n].float().mean().item())
-            lp3_steps += lp3 * n
-            agent_steps += n
-        else:
-            stats = np.array([0.0, 0.0, np.inf])
-            lp3 = 0.0
-        # leave at the goal
-        left = int(orca.remove_arrived(cur, _view(b, n), life_ws).item()) if n else 0
         arrived += n - left
         a, b = b, a
         if record:
