@@ -418,6 +418,31 @@ def bench_crossing():
     return {"metric": "crossings with spawning and removal, 2,500 agents per group", **out}
 
 
+def bench_sweep():
+    """A responsibility sweep: six tables f over 512 isolated head-on
+    pedestrian-vehicle encounters (1,024 agents), as six scenes of one
+    batched step, 80 steps; per table the pairs that ever overlap, the
+    smallest clearance, the LP3 share and the final mean speeds, and the
+    time per batched step of the whole sweep."""
+    import torch
+    from paper_2008_11578_amd import scenarios, sweeps
+    sc = scenarios.head_on_pairs(pairs=512)
+    tables = [sweeps.table(0.5, 1.0, 0.0, 0.5), sweeps.table(0.5, 0.5, 0.5, 0.5),
+              sweeps.table(0.5, 0.75, 0.25, 0.5), sweeps.table(0.5, 0.0, 1.0, 0.5),
+              sweeps.table(0.5, 0.25, 0.25, 0.5), sweeps.table(0.5, 0.0, 0.0, 0.5)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = sweeps.run(tables, sc, steps=sc.steps, reach=3.0)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    log(f"[bench] sweep {len(tables)} tables x {sc.n} agents x {sc.steps} steps: {el:.2f} s")
+    return {"metric": "responsibility sweep, six tables as six scenes of one batched step",
+            "scene": "512 isolated head-on pedestrian-vehicle pairs", "agents_per_table": sc.n,
+            "steps": sc.steps, "wall_s": el, "ms_per_step": el / sc.steps * 1e3,
+            "tables": [{k: (list(map(list, v)) if k == "f" else v) for k, v in r.items()}
+                       for r in res]}
+
+
 def bench_adjoint(reps: int = 3):
     """Differentiable rollout: 16,384 agents, 50 steps, checkpoints every 10:
     forward rollout, then the backward pass (segment replays and
@@ -476,6 +501,8 @@ def main(argv=None):
                     help="graph-captured steps of the 512-scene batched form (0 skips it)")
     ap.add_argument("--no-adjoint", dest="adjoint", action="store_false",
                     help="skip the differentiable-rollout leg")
+    ap.add_argument("--no-sweep", dest="sweep", action="store_false",
+                    help="skip the responsibility sweep")
     ap.add_argument("--no-crossing", dest="crossing", action="store_false",
                     help="skip the crossing runs with spawning and removal")
     ap.add_argument("--no-extensions", dest="extensions", action="store_false",
@@ -589,6 +616,7 @@ def main(argv=None):
     vshare = bench_vehicle_share() if args.vehicle_share else None
     ext = bench_extensions() if args.extensions else None
     cross = bench_crossing() if args.crossing else None
+    sweep = bench_sweep() if args.sweep else None
 
     out = {
         "metric": "agent-steps/sec at 1M agents (ORCA+LP); batched & adjoint steps/sec",
@@ -615,6 +643,7 @@ def main(argv=None):
         "vehicle_share": vshare,
         "extensions": ext,
         "crossing": cross,
+        "sweep": sweep,
     }
     print(json.dumps(out), flush=True)
     return 0
