@@ -19,11 +19,11 @@
 //                          (c = v, or v scaled onto the speed circle),
 //                   writing the agent's own cotangents and up to three
 //                   contributions to neighbours into an edge list;
-//   k_edge_*        counting sort of the edges by target, each target summing
-//                   its edges in source order (no floating-point atomics, so
-//                   results are bit-reproducible);
-//   k_tau_reduce    one block sums the per-agent tau contributions in a fixed
-//                   order, in double.
+//   k_edge_*,       counting sort of the edges by target (count, tiled scan,
+//   k_escan_*       place), each target summing its edges in source order (no
+//                   floating-point atomics, so results are bit-reproducible);
+//   k_tau_*         the per-agent tau contributions summed in double in a
+//                   fixed order (block sums, then one block).
 // Neighbour sets and branches are held fixed (they are piecewise constant).
 #include "orca_device.h"
 
@@ -467,28 +467,60 @@ __global__ __launch_bounds__(kBlock) void k_edge_count(const int32_t *__restrict
     if (t >= 0 && t < n) e_rank[e] = atomicAdd(&e_cnt[t], 1u);
 }
 
-// Exclusive scan of per-target counts (one block; n targets).
-__global__ __launch_bounds__(1024) void k_edge_scan(const uint32_t *__restrict__ cnt, int n,
-                                                    uint32_t *__restrict__ start)
+// Exclusive scan of the per-target counts in tiles of kScanTile: the sum of
+// each tile, one block scanning the tile sums, then the scan inside each
+// tile offset by its prefix.
+constexpr int kPer = kScanTile / kBlock;
+
+__global__ __launch_bounds__(kBlock) void k_escan_reduce(const uint32_t *__restrict__ cnt, int n,
+                                                         uint32_t *__restrict__ tiles)
 {
-    __shared__ uint32_t part[1024];
-    const int tid = threadIdx.x;
-    const int per = (n + 1023) / 1024;
-    const int lo = tid * per, hi = min(lo + per, n);
-    uint32_t sum = 0;
-    for (int k = lo; k < hi; ++k) sum += cnt[k];
-    part[tid] = sum;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t v = tid >= off ? part[tid - off] : 0u;
-        __syncthreads();
-        part[tid] += v;
+    const int base = blockIdx.x * kScanTile;
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int c = base + threadIdx.x * kPer + k;
+        if (c < n) s += cnt[c];
+    }
+    uint32_t tot;
+    block_excl_scan<kBlock>(s, &tot);
+    if (threadIdx.x == 0) tiles[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_escan_tiles(uint32_t *__restrict__ tiles, int nt)
+{
+    uint32_t carry = 0;
+    for (int b = 0; b < nt; b += kBlock) {
+        const int t = b + threadIdx.x;
+        const uint32_t v = t < nt ? tiles[t] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan<kBlock>(v, &tot);
+        if (t < nt) tiles[t] = carry + ex;
+        carry += tot;
         __syncthreads();
     }
-    uint32_t run = part[tid] - sum;
-    for (int k = lo; k < hi; ++k) {
-        start[k] = run;
-        run += cnt[k];
+}
+
+__global__ __launch_bounds__(kBlock) void k_escan_apply(const uint32_t *__restrict__ cnt, int n,
+                                                        const uint32_t *__restrict__ tiles,
+                                                        uint32_t *__restrict__ start)
+{
+    const int base = blockIdx.x * kScanTile;
+    uint32_t v[kPer];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int c = base + threadIdx.x * kPer + k;
+        v[k] = c < n ? cnt[c] : 0u;
+        s += v[k];
+    }
+    uint32_t tot;
+    uint32_t run = tiles[blockIdx.x] + block_excl_scan<kBlock>(s, &tot);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        const int c = base + threadIdx.x * kPer + k;
+        if (c < n) start[c] = run;
+        run += v[k];
     }
 }
 
@@ -537,16 +569,33 @@ __global__ __launch_bounds__(kBlock) void k_edge_gather(int n, const uint32_t *_
     gvy0[j] += ty;
 }
 
-// g_tau += sum of the per-agent contributions, fixed order, in double.
-__global__ __launch_bounds__(1024) void k_tau_reduce(const float *__restrict__ part, int n,
-                                                     float *g_tau)
+// g_tau += sum of the per-agent contributions in double, in a fixed order:
+// kTauBlocks blocks each reduce a contiguous share (threads strided, then a
+// tree), and one block adds the block sums by a tree.
+__global__ __launch_bounds__(kBlock) void k_tau_partial(const float *__restrict__ part, int n,
+                                                        double *__restrict__ blocks)
 {
-    __shared__ double red[1024];
+    __shared__ double red[kBlock];
+    const int per = (n + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int a = blockIdx.x * per, b = min(a + per, n);
     double s = 0.0;
-    for (int k = threadIdx.x; k < n; k += 1024) s += (double)part[k];
+    for (int k = a + threadIdx.x; k < b; k += kBlock) s += (double)part[k];
     red[threadIdx.x] = s;
     __syncthreads();
-    for (int off = 512; off > 0; off >>= 1) {
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) blocks[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kTauBlocks) void k_tau_final(const double *__restrict__ blocks,
+                                                          float *g_tau)
+{
+    __shared__ double red[kTauBlocks];
+    red[threadIdx.x] = blocks[threadIdx.x];
+    __syncthreads();
+    for (int off = kTauBlocks / 2; off > 0; off >>= 1) {
         if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
         __syncthreads();
     }
@@ -617,13 +666,21 @@ hipError_t launch_adjoint(const orca_agents_in &in, int n, const orca_params &pr
     const int nbe = (ne + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_edge_count, dim3(nbe), dim3(kBlock), 0, stream, b.e_tgt, ne, n, b.e_cnt,
                        b.e_rank);
-    hipLaunchKernelGGL(k_edge_scan, dim3(1), dim3(1024), 0, stream, b.e_cnt, n, b.e_start);
+    const int nt = (n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_escan_reduce, dim3(nt), dim3(kBlock), 0, stream, b.e_cnt, n, b.e_tiles);
+    hipLaunchKernelGGL(k_escan_tiles, dim3(1), dim3(kBlock), 0, stream, b.e_tiles, nt);
+    hipLaunchKernelGGL(k_escan_apply, dim3(nt), dim3(kBlock), 0, stream, b.e_cnt, n, b.e_tiles,
+                       b.e_start);
     hipLaunchKernelGGL(k_edge_place, dim3(nbe), dim3(kBlock), 0, stream, b.e_tgt, ne, n, b.e_rank,
                        b.e_start, b.e_list);
     hipLaunchKernelGGL(k_edge_gather, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, stream, n,
                        b.e_cnt, b.e_start, b.e_list, b.e_val, gpx0, gpy0, gvx0, gvy0);
-    if (g_tau)
-        hipLaunchKernelGGL(k_tau_reduce, dim3(1), dim3(1024), 0, stream, b.tau_part, n, g_tau);
+    if (g_tau) {
+        hipLaunchKernelGGL(k_tau_partial, dim3(kTauBlocks), dim3(kBlock), 0, stream, b.tau_part,
+                           n, b.tau_blocks);
+        hipLaunchKernelGGL(k_tau_final, dim3(1), dim3(kTauBlocks), 0, stream, b.tau_blocks,
+                           g_tau);
+    }
     return hipGetLastError();
 }
 

@@ -73,7 +73,9 @@ size_t adjoint_extra_bytes(int64_t n)
     const size_t a = align_up(sizeof(float) * (size_t)n) + align_up(sizeof(int32_t) * 3 * (size_t)n) +
                      align_up(sizeof(float4) * 3 * (size_t)n) +
                      2 * align_up(sizeof(uint32_t) * 3 * (size_t)n) +
-                     2 * align_up(sizeof(uint32_t) * (size_t)n);
+                     2 * align_up(sizeof(uint32_t) * (size_t)n) +
+                     align_up(sizeof(uint32_t) * (size_t)((n + kScanTile - 1) / kScanTile + 1)) +
+                     align_up(sizeof(double) * kTauBlocks);
     return a;
 }
 
@@ -95,6 +97,10 @@ AdjointBufs bind_adjoint(int64_t n, void *base)
     r.e_cnt = (uint32_t *)(b + o);
     o += align_up(sizeof(uint32_t) * (size_t)n);
     r.e_start = (uint32_t *)(b + o);
+    o += align_up(sizeof(uint32_t) * (size_t)n);
+    r.e_tiles = (uint32_t *)(b + o);
+    o += align_up(sizeof(uint32_t) * (size_t)((n + kScanTile - 1) / kScanTile + 1));
+    r.tau_blocks = (double *)(b + o);
     return r;
 }
 

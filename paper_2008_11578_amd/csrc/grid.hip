@@ -79,37 +79,6 @@ __global__ __launch_bounds__(kBlock) void k_cell_count(const float *__restrict__
     rank[i] = atomicAdd(&count[c], 1u);
 }
 
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
-{
-    const int lane = threadIdx.x % kWave;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const uint32_t t = __shfl_up(v, o, kWave);
-        if (lane >= o) v += t;
-    }
-    return v;
-}
-
-// Exclusive block scan of one value per thread; returns the exclusive prefix
-// and writes the block total to *total (all threads).
-__device__ uint32_t block_excl_scan(uint32_t v, uint32_t *total)
-{
-    __shared__ uint32_t wsum[kBlock / kWave];
-    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-    const uint32_t inc = wave_incl_scan(v);
-    if (lane == kWave - 1) wsum[wid] = inc;
-    __syncthreads();
-    uint32_t base = 0, tot = 0;
-#pragma unroll
-    for (int k = 0; k < kBlock / kWave; ++k) {
-        if (k < wid) base += wsum[k];
-        tot += wsum[k];
-    }
-    __syncthreads();
-    *total = tot;
-    return base + inc - v;
-}
-
 constexpr int kPer = kScanTile / kBlock;  // 8 cells per thread
 
 // (4a) per-tile sums of the histogram.
@@ -127,7 +96,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t *__restri
         if (c < n_cells) s += count[c];
     }
     uint32_t tot;
-    block_excl_scan(s, &tot);
+    block_excl_scan<kBlock>(s, &tot);
     if (threadIdx.x == 0) tiles[blockIdx.x] = tot;
 }
 
@@ -141,7 +110,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(uint32_t *__restrict__ ti
         const int t = b + threadIdx.x;
         const uint32_t v = t < nt ? tiles[t] : 0u;
         uint32_t tot;
-        const uint32_t ex = block_excl_scan(v, &tot);
+        const uint32_t ex = block_excl_scan<kBlock>(v, &tot);
         if (t < nt) tiles[t] = carry + ex;
         carry += tot;
         __syncthreads();
@@ -166,7 +135,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const uint32_t *__restric
         s += v[k];
     }
     uint32_t tot;
-    uint32_t run = tiles[blockIdx.x] + block_excl_scan(s, &tot);
+    uint32_t run = tiles[blockIdx.x] + block_excl_scan<kBlock>(s, &tot);
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         const int c = base + threadIdx.x * kPer + k;

@@ -78,6 +78,39 @@ __device__ __forceinline__ float wave_max(float v)
     return v;
 }
 
+// Inclusive prefix sum over the 64 lanes of a wavefront.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v)
+{
+    const int lane = threadIdx.x % kWave;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t t = __shfl_up(v, o, kWave);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Exclusive block scan of one value per thread; returns the exclusive prefix
+// and writes the block total to *total (all threads).
+template <int BLOCK>
+__device__ uint32_t block_excl_scan(uint32_t v, uint32_t *total)
+{
+    __shared__ uint32_t wsum[BLOCK / kWave];
+    const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+    const uint32_t inc = wave_incl_scan(v);
+    if (lane == kWave - 1) wsum[wid] = inc;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < BLOCK / kWave; ++k) {
+        if (k < wid) base += wsum[k];
+        tot += wsum[k];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + inc - v;
+}
+
 // Block-wide (min x, min y, max x, max y).  Result valid in thread 0.
 template <int kBlock>
 __device__ float4 block_bbox(float4 b)
@@ -225,7 +258,11 @@ struct AdjointBufs {
     uint32_t *e_list;    // 3n
     uint32_t *e_cnt;     // n
     uint32_t *e_start;   // n
+    uint32_t *e_tiles;   // ceil(n / kScanTile) tile prefixes of the count scan
+    double *tau_blocks;  // kTauBlocks partial sums of the tau contributions
 };
+
+constexpr int kTauBlocks = 256;
 
 size_t adjoint_extra_bytes(int64_t n);
 AdjointBufs bind_adjoint(int64_t n, void *base);
