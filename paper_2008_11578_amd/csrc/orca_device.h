@@ -54,8 +54,10 @@ __device__ __forceinline__ double nb_key(float xi, float yi, float xj, float yj)
 // coordinates), so every agent with key < R_n^2 is visited.
 //
 // Pass 1 counts the in-range candidates of the lane in kBins bins of equal
-// area (bin = floor(key * kBins / R_n^2), monotone in the key); the counts
-// are 8-bit fields of two 64-bit registers.  The first bin b* at which the
+// area (bin = floor(key * kBins / R_n^2), monotone in the key); a group of
+// candidates adds to 4-bit fields of one 64-bit register, which are then
+// widened into the 8-bit fields of two (even and odd bins).  The first bin
+// b* at which the
 // running count reaches k is the threshold: every candidate of a lower bin is
 // among the k nearest and the rest of the k nearest lie in bin b*.
 // Pass 2 visits only the circle that holds bins <= b* and appends their
@@ -121,15 +123,19 @@ __device__ __forceinline__ bool entry_less(uint64_t ea, uint64_t eb, const float
 constexpr int kScanUnroll = ORCA_SCAN_UNROLL;
 static_assert(kScanUnroll <= kScanPad, "candidate groups may read at most kScanPad past s0");
 
+struct NoGroupEnd {
+    __device__ __forceinline__ void operator()() const {}
+};
+
 // Visits the cell-order candidates [ra, rb) (ra < rb) in groups of
-// kScanUnroll as visit(c, t, valid) (c = s0[t]).  A group always loads all its members
-// (the last one reads up to kScanUnroll - 1 entries past rb, inside s0 and
-// its padding) and passes valid = t < rb, so the visitor runs without a
-// remainder loop and can stay branch-free.  The next group is loaded before
-// the current one is visited.
-template <class F>
+// kScanUnroll as visit(c, t, valid) (c = s0[t]), calling group_end() after
+// each group.  A group always loads all its members (the last one reads up
+// to kScanUnroll - 1 entries past rb, inside s0 and its padding) and passes
+// valid = t < rb, so the visitor runs without a remainder loop and can stay
+// branch-free.  The next group is loaded before the current one is visited.
+template <class F, class G = NoGroupEnd>
 __device__ __forceinline__ void scan_range(const float4 *__restrict__ s0, uint32_t ra, uint32_t rb,
-                                           F &&visit)
+                                           F &&visit, G &&group_end = G())
 {
     // two register groups used in turn, so no group is copied; components a
     // visitor does not read are never loaded
@@ -145,6 +151,7 @@ __device__ __forceinline__ void scan_range(const float4 *__restrict__ s0, uint32
         }
 #pragma unroll
         for (int q = 0; q < kScanUnroll; ++q) visit(c[q], t + q, t + q < rb);
+        group_end();
         if (!more1) break;
         const bool more2 = t + 2 * kScanUnroll < rb;
         if (more2) {
@@ -154,6 +161,7 @@ __device__ __forceinline__ void scan_range(const float4 *__restrict__ s0, uint32
         const uint32_t u = t + kScanUnroll;
 #pragma unroll
         for (int q = 0; q < kScanUnroll; ++q) visit(d[q], u + q, u + q < rb);
+        group_end();
         if (!more2) break;
         p += 2 * kScanUnroll;
     }
@@ -230,10 +238,10 @@ __device__ __forceinline__ void sort_network(uint64_t (&e)[N])
 // Visits every candidate in the grid rows and chords of the circle of
 // squared radius r2 around (xd, yd), row by row; the next row's range (two
 // loads from `start`) is requested before the current row is scanned.
-template <class F>
+template <class F, class G = NoGroupEnd>
 __device__ __forceinline__ void scan_disc(const GridMeta &g, const uint32_t *__restrict__ start,
                                           const float4 *__restrict__ s0, double xd, double yd,
-                                          double r2, F &&visit)
+                                          double r2, F &&visit, G &&group_end = G())
 {
     int ya, yb;
     row_span(g, yd, r2, ya, yb);
@@ -243,7 +251,7 @@ __device__ __forceinline__ void scan_disc(const GridMeta &g, const uint32_t *__r
         const uint32_t ra = na, rb = nb;
         const bool ok = nok;
         if (yy < yb) nok = row_range(g, start, xd, yd, r2, yy + 1, na, nb);
-        if (ok) scan_range(s0, ra, rb, visit);
+        if (ok) scan_range(s0, ra, rb, visit, group_end);
     }
 }
 
@@ -267,27 +275,40 @@ __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
     // test out of this loop.
     double r2c = rg2 < g.rn2 ? rg2 : g.rn2;
     double bscale;
-    uint64_t hlo, hhi;
+    // Counts per bin: 4-bit counters of one group of candidates in `nib`
+    // (a group adds at most kScanUnroll <= 15 to a bin), widened after each
+    // group into byte counters, even bins in `hev` (byte k: bin 2k) and odd
+    // bins in `hod` (byte k: bin 2k + 1); bytes cannot overflow either, since
+    // a lane with more than 255 candidates takes the exact fallback below.
+    static_assert(kScanUnroll <= 15, "a group must fit the 4-bit counters");
+    uint64_t hev, hod, nib;
     uint32_t total;
     for (;;) {
         bscale = (double)kBins / r2c;
-        hlo = 0;
-        hhi = 0;
+        hev = 0;
+        hod = 0;
+        nib = 0;
         total = 0;
-        scan_disc(g, start, s0, xd, yd, r2c, [&](const float4 &c, uint32_t t, bool valid) {
-            const double key = nb_key(xi, yi, c.x, c.y);
-            const bool in = valid && key < r2c;
-            // equals min((int)(key * bscale), kBins - 1) for every key, and is
-            // defined also for the far (or invalid) candidates it is not used for
-            const int bin = (int)fmin(key * bscale, (double)(kBins - 1));
-            const int sh = (bin & 7) * 8;
-            hlo += (uint64_t)(in && bin < 8 ? 1u : 0u) << sh;
-            hhi += (uint64_t)(in && bin >= 8 ? 1u : 0u) << sh;
-            if (in && total < (uint32_t)kCap)
-                buf[buf_idx<BLOCK>((int)total, tid)] = pack_entry(key, t, (uint32_t)bin);
-            total += in ? 1u : 0u;
-        });
-        hlo -= 1ull;
+        scan_disc(
+            g, start, s0, xd, yd, r2c,
+            [&](const float4 &c, uint32_t t, bool valid) {
+                const double key = nb_key(xi, yi, c.x, c.y);
+                const bool in = valid && key < r2c;
+                // equals min((int)(key * bscale), kBins - 1) for every key, and
+                // is defined also for the far (or invalid) candidates it is not
+                // used for
+                const int bin = (int)fmin(key * bscale, (double)(kBins - 1));
+                nib += (uint64_t)(in ? 1u : 0u) << (bin * 4);
+                if (in && total < (uint32_t)kCap)
+                    buf[buf_idx<BLOCK>((int)total, tid)] = pack_entry(key, t, (uint32_t)bin);
+                total += in ? 1u : 0u;
+            },
+            [&]() {
+                hev += nib & 0x0F0F0F0F0F0F0F0Full;
+                hod += (nib >> 4) & 0x0F0F0F0F0F0F0F0Full;
+                nib = 0;
+            });
+        hev -= 1ull;  // the lane's own entry, key 0, bin 0
         total -= 1u;
         if (total >= (uint32_t)K || !(r2c < g.rn2)) break;
         r2c = g.rn2;  // the guessed circle holds fewer than K: count them all
@@ -301,7 +322,7 @@ __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
     bool found = false;
 #pragma unroll
     for (int b = 0; b < kBins; ++b) {
-        cum += (uint32_t)(((b < 8 ? hlo : hhi) >> ((b & 7) * 8)) & 0xffull);
+        cum += (uint32_t)((((b & 1) ? hod : hev) >> ((b >> 1) * 8)) & 0xffull);
         if (!found && cum >= (uint32_t)K) {
             found = true;
             bstar = b;
