@@ -203,3 +203,24 @@ def test_backward_accepts_acceleration_caps(orca_mod):
                                   ctypes.byref(g0), FAKE, 64, None) == -2
     assert lib.orca_step_backward(ctypes.byref(ain), 100, ctypes.byref(bad), ctypes.byref(g1),
                                   ctypes.byref(g0), FAKE, 64, None) == -1
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """With no liborca.so the binding raises instead of falling back to
+    anything else (there is no CPU path)."""
+    import subprocess
+    import sys
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import paper_2008_11578_amd.orca as o\n"
+        "o.LIB_PATH = %r\n"
+        "o._lib = None\n"
+        "try:\n"
+        "    o.lib()\n"
+        "except Exception as e:\n"
+        "    print(type(e).__name__, e)\n"
+        "    sys.exit(3)\n"
+        "sys.exit(0)\n" % (ROOT, str(tmp_path / "liborca.so")))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 3, (r.stdout, r.stderr)
+    assert "missing" in r.stdout
