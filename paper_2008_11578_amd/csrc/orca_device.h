@@ -82,6 +82,12 @@ struct KnnShape {
 constexpr int kHard = 8;
 
 // Entry e of lane `tid` inside a [slot][BLOCK] float4 array viewed as u64.
+// Both entries of a 16-byte slot stay in the lane's own column tid: the
+// buffer shares the LDS of the half-planes, and the wavefronts of a block
+// run independently, so a lane that has reached its half-planes may only
+// overwrite its own column.  (An [entry][BLOCK] layout would place a lane's
+// entries in other lanes' columns, where a wavefront already writing
+// half-planes corrupts one still selecting.)
 template <int BLOCK>
 __device__ __forceinline__ int buf_idx(int e, int tid)
 {
