@@ -54,10 +54,14 @@ def log(*a):
 
 
 def source_hash() -> str:
+    """Hash of the step kernel's source (comments removed, so that only a
+    change of code invalidates the committed counter summaries)."""
     h = hashlib.sha256()
     for f in ("step.hip", "orca_device.h", "orca_internal.h"):
-        with open(os.path.join(ROOT, "paper_2008_11578_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2008_11578_amd", "csrc", f)) as fh:
+            code = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        code = re.sub(r"//[^\n]*", "", code)
+        h.update(code.encode())
     return h.hexdigest()[:16]
 
 
