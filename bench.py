@@ -214,7 +214,8 @@ def bench_batched(steps: int):
     nxt = st.clone()
     ws = orca.Workspace(n, n_scenes=S)
     tuned = autotune.tune_batched(st, sc.scene_off, sc.scene_params, ws, reps=3, use_cache=False)
-    batch = orca.Batch(sc.scene_off, tuned["params"], mode=tuned["mode"])
+    batch = orca.Batch(sc.scene_off, tuned["params"], mode=tuned["mode"], block=tuned["block"],
+                       k_tile=tuned["k_tile"])
     graph, _ = capture_loop(lambda x, y: orca.step_batched(x, batch, ws, out=y), st, nxt, steps)
     graph.replay()
     torch.cuda.synchronize()
@@ -255,13 +256,15 @@ def bench_batched(steps: int):
     torch.cuda.synchronize()
     ms_ps = (time.perf_counter() - t0) * 1e3 / 2
     log(f"[bench] batched {S} scenes, {n} agents: {ms:.3f} ms/step (graph of {steps}), "
-        f"per-scene {ms_ps:.3f} ms/step, tuned factor {tuned['factor']:.3f} mode {tuned['mode']}")
+        f"per-scene {ms_ps:.3f} ms/step, tuned factor {tuned['factor']:.3f} mode {tuned['mode']} "
+        f"block {tuned['block']} k tile {tuned['k_tile']}")
     return {"metric": "scene-steps/s (512 uneven scenes, one batched step per graph node set)",
             "scenes": S, "agents": n, "ms_per_step": ms,
             "scene_steps_per_s": S / (ms * 1e-3), "agent_steps_per_s": n / (ms * 1e-3),
             "per_scene_ms_per_step": ms_ps, "speedup_vs_per_scene": ms_ps / ms,
             "graph_steps": steps, "tuned": {"cell_factor": tuned["factor"],
-                                             "mode": tuned["mode"]}}
+                                             "mode": tuned["mode"], "block": tuned["block"],
+                                             "k_tile": tuned["k_tile"]}}
 
 
 def bench_vehicle_share(steps: int = 100, warmup: int = 10):

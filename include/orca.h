@@ -166,6 +166,14 @@ typedef struct {
     int32_t has_accel;            /* HOST: 1 if any scene has accel[c] > 0 (selects
                                      the kernel with acceleration lines; without it
                                      caps are ignored and flagged), else 0 */
+    int32_t block;                /* HOST: lanes per workgroup of the step kernel,
+                                     64, 128 or 256 (1, 2 or 4 wavefronts); 0 = 128 */
+    int32_t k_tile;               /* HOST: neighbour-list capacity compiled into the
+                                     step kernel, max_neighbors..ORCA_K_MAX, rounded
+                                     up to a compiled one (4, 8, 10, 12, 16, 20, 24,
+                                     32); 0 = the smallest that holds max_neighbors.
+                                     Results do not depend on it (the k nearest are
+                                     the first k of any larger nearest set). */
 } orca_batch;
 
 /* One ORCA step of every scene of a batch.  n is the total agent count; the

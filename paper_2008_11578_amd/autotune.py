@@ -1,7 +1,8 @@
 """Autotuner for the ORCA step: picks the grid cell size (as a fraction of
 the neighbour distance) and, for batches, the launch form of the step kernel
-(persistent with per-XCD tile queues, or one workgroup per tile), by timing
-real steps on the caller's state.
+(persistent with per-XCD tile queues, or one workgroup per tile), the lanes
+per workgroup and the compiled neighbour-list capacity, by timing real steps
+on the caller's state.
 
 Results are cached in a JSON file keyed by device architecture, form, agent
 count bucket (powers of two), density bucket (half-octaves of agents/m^2) and
@@ -108,25 +109,43 @@ def tune_plain(state: orca.State, params, ws: orca.Workspace,
     return dict(res, cell_size=best * params.neighbor_dist, cached=False)
 
 
+BLOCKS = (64, 128, 256)
+K_TILES = (4, 8, 10, 12, 16, 20, 24, 32)  # neighbour capacities compiled into the kernels
+
+
 def tune_batched(state: orca.State, scene_off, scene_params: List, ws: orca.Workspace,
                  factors: Sequence[float] = FACTORS, modes: Iterable[int] = MODES,
-                 reps: int = 5, use_cache: bool = True) -> dict:
-    """Best (cell-size factor, launch mode) for orca_step_batched.  Returns
-    {"factor", "mode", "ms", "timings", "params" (tuned per-scene list)}."""
+                 blocks: Sequence[int] = BLOCKS, reps: int = 5,
+                 use_cache: bool = True) -> dict:
+    """Best (cell-size factor, launch form, lanes per workgroup, neighbour
+    tile) for orca_step_batched, by coordinate search in that order, each
+    stage timing its candidates with the choices made so far (the tile: the
+    smallest compiled capacity holding k and the next two).  Returns
+    {"factor", "mode", "block", "k_tile", "ms", "timings", "params" (tuned
+    per-scene list)}."""
     k = max(int(p.max_neighbors) for p in scene_params)
     key = cache_key(f"batched{len(scene_params)}", state.n, _density(state), k)
     hit = _load().get(key) if use_cache else None
     if hit is None:
         out = state.clone()
         timings = {}
-        for f in factors:
+
+        def run(f, m, b, kt):
             prm = [dataclasses.replace(p, cell_size=f * p.neighbor_dist) for p in scene_params]
-            for m in modes:
-                b = orca.Batch(scene_off, prm, mode=m)
-                timings[(f, m)] = _time_ms(lambda: orca.step_batched(state, b, ws, out=out), reps)
-        best = min(timings, key=timings.get)
-        hit = {"factor": best[0], "mode": best[1], "ms": timings[best],
-               "timings": {f"{f:.4f}/{m}": v for (f, m), v in timings.items()}}
+            batch = orca.Batch(scene_off, prm, mode=m, block=b, k_tile=kt)
+            t = _time_ms(lambda: orca.step_batched(state, batch, ws, out=out), reps)
+            timings[f"{f:.4f}/{m}/{b}/{kt}"] = t
+            return t
+
+        best = {"factor": factors[0], "mode": 0, "block": 128, "k_tile": 0}
+        f = min(factors, key=lambda f: run(f, best["mode"], best["block"], best["k_tile"]))
+        best["factor"] = f
+        best["mode"] = min(modes, key=lambda m: run(f, m, best["block"], best["k_tile"]))
+        best["block"] = min(blocks, key=lambda b: run(f, best["mode"], b, best["k_tile"]))
+        tiles = [t for t in K_TILES if t >= k][:3]
+        best["k_tile"] = min(tiles, key=lambda kt: run(f, best["mode"], best["block"], kt))
+        best["ms"] = timings[f"{f:.4f}/{best['mode']}/{best['block']}/{best['k_tile']}"]
+        hit = dict(best, timings=timings)
         _store(key, hit)
         cached = False
     else:

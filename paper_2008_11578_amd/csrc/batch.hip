@@ -217,34 +217,44 @@ int persistent_grid()
     return g;
 }
 
-template <int K, bool ACC>
+template <int K, int BLOCK, bool ACC>
 hipError_t launch_step_batched_v(const BatchArgs &a, int mode, hipStream_t stream)
 {
     if (mode == 1) {
-        const int nb = (a.n + kStepBlock - 1) / kStepBlock;
-        hipLaunchKernelGGL((k_step_batched_flat<K, kStepBlock, ACC>), dim3(nb), dim3(kStepBlock),
-                           0, stream, a);
+        const int nb = (a.n + BLOCK - 1) / BLOCK;
+        hipLaunchKernelGGL((k_step_batched_flat<K, BLOCK, ACC>), dim3(nb), dim3(BLOCK), 0, stream,
+                           a);
         return hipGetLastError();
     }
-    const int g = persistent_grid<K, kStepBlock, ACC>();
+    const int g = persistent_grid<K, BLOCK, ACC>();
     if (g <= 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_step_batched<K, kStepBlock, ACC>), dim3(g), dim3(kStepBlock), 0, stream,
-                       a);
+    hipLaunchKernelGGL((k_step_batched<K, BLOCK, ACC>), dim3(g), dim3(BLOCK), 0, stream, a);
     return hipGetLastError();
 }
 
-template <int K>
-hipError_t launch_step_batched_k(const BatchArgs &a, int mode, bool acc, hipStream_t stream)
+template <int K, int BLOCK>
+hipError_t launch_step_batched_b(const BatchArgs &a, int mode, bool acc, hipStream_t stream)
 {
-    return acc ? launch_step_batched_v<K, true>(a, mode, stream)
-               : launch_step_batched_v<K, false>(a, mode, stream);
+    return acc ? launch_step_batched_v<K, BLOCK, true>(a, mode, stream)
+               : launch_step_batched_v<K, BLOCK, false>(a, mode, stream);
+}
+
+// Workgroup size (one, two or four wavefronts; the LDS column per lane is
+// the same, so occupancy differs only through the workgroup granularity).
+template <int K>
+hipError_t launch_step_batched_k(const BatchArgs &a, int mode, bool acc, int block,
+                                 hipStream_t stream)
+{
+    if (block == 64) return launch_step_batched_b<K, 64>(a, mode, acc, stream);
+    if (block == 256) return launch_step_batched_b<K, 256>(a, mode, acc, stream);
+    return launch_step_batched_b<K, kStepBlock>(a, mode, acc, stream);
 }
 
 }  // namespace
 
 hipError_t launch_batched(const orca_agents_in &in, const orca_agents_out &out, int n,
                           const int32_t *scene_off, int n_scenes, const orca_params *params,
-                          int k_max, bool acc, const Layout &L, const Work &w,
+                          int k_max, bool acc, int block, const Layout &L, const Work &w,
                           int32_t *error_flag, int mode, hipStream_t stream)
 {
     const int S = n_scenes;
@@ -271,14 +281,14 @@ hipError_t launch_batched(const orca_agents_in &in, const orca_agents_out &out, 
     a.s1 = w.s1;
     a.queue = w.queue;
     a.guess = w.guess;
-    if (k_max <= 4) return launch_step_batched_k<4>(a, mode, acc, stream);
-    if (k_max <= 8) return launch_step_batched_k<8>(a, mode, acc, stream);
-    if (k_max <= 10) return launch_step_batched_k<10>(a, mode, acc, stream);
-    if (k_max <= 12) return launch_step_batched_k<12>(a, mode, acc, stream);
-    if (k_max <= 16) return launch_step_batched_k<16>(a, mode, acc, stream);
-    if (k_max <= 20) return launch_step_batched_k<20>(a, mode, acc, stream);
-    if (k_max <= 24) return launch_step_batched_k<24>(a, mode, acc, stream);
-    return launch_step_batched_k<32>(a, mode, acc, stream);
+    if (k_max <= 4) return launch_step_batched_k<4>(a, mode, acc, block, stream);
+    if (k_max <= 8) return launch_step_batched_k<8>(a, mode, acc, block, stream);
+    if (k_max <= 10) return launch_step_batched_k<10>(a, mode, acc, block, stream);
+    if (k_max <= 12) return launch_step_batched_k<12>(a, mode, acc, block, stream);
+    if (k_max <= 16) return launch_step_batched_k<16>(a, mode, acc, block, stream);
+    if (k_max <= 20) return launch_step_batched_k<20>(a, mode, acc, block, stream);
+    if (k_max <= 24) return launch_step_batched_k<24>(a, mode, acc, block, stream);
+    return launch_step_batched_k<32>(a, mode, acc, block, stream);
 }
 
 }  // namespace orca

@@ -262,6 +262,10 @@ int orca_step_batched(const orca_agents_in *in, const orca_agents_out *out, int3
     if (batch->max_neighbors < 1 || batch->max_neighbors > ORCA_K_MAX) return ORCA_ERANGE;
     if (batch->mode != 0 && batch->mode != 1) return ORCA_EINVAL;
     if (batch->has_accel != 0 && batch->has_accel != 1) return ORCA_EINVAL;
+    if (batch->block != 0 && batch->block != 64 && batch->block != 128 && batch->block != 256)
+        return ORCA_EINVAL;
+    if (batch->k_tile != 0 && (batch->k_tile < batch->max_neighbors || batch->k_tile > ORCA_K_MAX))
+        return ORCA_ERANGE;
     if (n == 0) return ORCA_OK;
     int rc = check_in(in);
     if (rc != ORCA_OK) return rc;
@@ -273,8 +277,9 @@ int orca_step_batched(const orca_agents_in *in, const orca_agents_out *out, int3
     if (L.total > ws_bytes) return ORCA_EWORKSPACE;
     const Work w = bind(L, ws);
     if (launch_batched(*in, *out, n, batch->scene_off, batch->n_scenes, batch->params,
-                       batch->max_neighbors, batch->has_accel != 0, L, w, batch->error_flag,
-                       batch->mode, stream) != hipSuccess)
+                       batch->k_tile ? batch->k_tile : batch->max_neighbors,
+                       batch->has_accel != 0, batch->block ? batch->block : 128, L, w,
+                       batch->error_flag, batch->mode, stream) != hipSuccess)
         return ORCA_EHIP;
     return ORCA_OK;
 }

@@ -222,7 +222,7 @@ hipError_t launch_scan_scatter(const orca_agents_in &in, int n, const Layout &L,
 // [off[s], off[s+1]) and cells [2 off[s] + 64 s, 2 off[s+1] + 64 (s + 1)).
 hipError_t launch_batched(const orca_agents_in &in, const orca_agents_out &out, int n,
                           const int32_t *scene_off, int n_scenes, const orca_params *params,
-                          int k_max, bool acc, const Layout &L, const Work &w,
+                          int k_max, bool acc, int block, const Layout &L, const Work &w,
                           int32_t *error_flag, int mode, hipStream_t stream);
 
 // Fused neighbour search + half-planes + LP + update for one scene.

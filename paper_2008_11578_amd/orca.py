@@ -50,7 +50,8 @@ class OrcaBatch(ctypes.Structure):
     _fields_ = [("scene_off", ctypes.c_void_p), ("n_scenes", ctypes.c_int32),
                 ("params", ctypes.c_void_p), ("max_neighbors", ctypes.c_int32),
                 ("mode", ctypes.c_int32), ("error_flag", ctypes.c_void_p),
-                ("has_accel", ctypes.c_int32)]
+                ("has_accel", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("k_tile", ctypes.c_int32)]
 
 
 class Cotangents(ctypes.Structure):
@@ -293,7 +294,8 @@ class Batch:
     """Scene offsets, per-scene parameters and the error flag of a batch, on
     the device (``orca_batch``)."""
 
-    def __init__(self, scene_off, scene_params, device="cuda", mode: int = 0):
+    def __init__(self, scene_off, scene_params, device="cuda", mode: int = 0, block: int = 0,
+                 k_tile: int = 0):
         import numpy as np
         off = np.ascontiguousarray(np.asarray(scene_off), dtype=np.int32)
         self.n_scenes = int(off.shape[0] - 1)
@@ -307,11 +309,13 @@ class Batch:
         self.has_accel = int(any(make_params(p).accel[c] > 0 for p in scene_params
                                  for c in range(2)))
         self.mode = int(mode)
+        self.block = int(block)    # lanes per workgroup (64, 128, 256; 0 = 128)
+        self.k_tile = int(k_tile)  # compiled neighbour capacity (0 = smallest >= k)
         self.error = torch.zeros(1, dtype=torch.int32, device=device)
 
     def c_struct(self) -> OrcaBatch:
         return OrcaBatch(_ptr(self.off), self.n_scenes, _ptr(self.params), self.max_neighbors,
-                         self.mode, _ptr(self.error), self.has_accel)
+                         self.mode, _ptr(self.error), self.has_accel, self.block, self.k_tile)
 
 
 def step_batched(state: State, batch: Batch, ws: Workspace, out: Optional[State] = None,

@@ -36,7 +36,7 @@ def test_struct_sizes_match_header(orca_mod):
     assert ctypes.sizeof(orca_mod.OrcaParams) == 4 * 4 + 4 + 4 + 16 + 4 + 8
     assert ctypes.sizeof(orca_mod.AgentsIn) == 9 * 8
     assert ctypes.sizeof(orca_mod.AgentsOut) == 5 * 8
-    assert ctypes.sizeof(orca_mod.OrcaBatch) == 8 + 4 + 4 + 8 + 4 + 4 + 8 + 8
+    assert ctypes.sizeof(orca_mod.OrcaBatch) == 8 + 4 + 4 + 8 + 4 + 4 + 8 + 8 + 8
 
 
 def test_status_strings(orca_mod):
@@ -127,7 +127,7 @@ def test_batched_argument_errors(orca_mod):
     ain, aout = _in_fake(orca_mod), _out_fake(orca_mod)
     B = orca_mod.OrcaBatch
     good = dict(scene_off=FAKE, n_scenes=2, params=FAKE, max_neighbors=16, mode=0, error_flag=None,
-                has_accel=0)
+                has_accel=0, block=0, k_tile=0)
 
     def call(n=100, ws_bytes=1 << 30, **kw):
         d = dict(good)
@@ -145,6 +145,9 @@ def test_batched_argument_errors(orca_mod):
     assert call(max_neighbors=40) == -4
     assert call(mode=7) == -1
     assert call(has_accel=2) == -1
+    assert call(block=96) == -1
+    assert call(k_tile=8) == -4    # below max_neighbors
+    assert call(k_tile=33) == -4
     assert call(ws_bytes=1024) == -2
 
 

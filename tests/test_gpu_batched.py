@@ -228,3 +228,43 @@ def test_responsibility_sweep_crowd_runs():
         assert 0 <= r["final_overlap_pairs"] <= r["worst_overlap_pairs"]
         assert r["worst_overlap_agents"] <= sc.n and np.isfinite(r["min_clearance"])
         assert 0 < r["mean_speed_ped"] <= 1.5 + 1e-6 and 0 < r["mean_speed_veh"] <= 6 + 1e-5
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("block,k_tile", [(64, 0), (256, 0), (128, 24), (256, 32)])
+def test_batched_block_and_tile_equal_single_scene_steps(mode, block, k_tile):
+    """Lanes per workgroup and the compiled neighbour capacity are
+    performance choices only: every scene still equals its plain step bit
+    for bit."""
+    import torch
+    from paper_2008_11578_amd import orca
+    sizes = [300, 1, 2000, 64, 900]
+    parts, prm, off, cat = _batch(sizes, seed=33)
+    st = orca.State.from_arrays(cat)
+    b = orca.Batch(off, prm, mode=mode, block=block, k_tile=k_tile)
+    out = orca.step_batched(st, b, orca.Workspace(st.n, n_scenes=len(sizes)))
+    torch.cuda.synchronize()
+    assert int(b.error.item()) == 0
+    for s, p in enumerate(parts):
+        if p.n == 0:
+            continue
+        o1 = orca.step(orca.State.from_arrays(p), prm[s], orca.Workspace(p.n))
+        torch.cuda.synchronize()
+        for k in ("vx", "vy", "px", "py"):
+            assert torch.equal(getattr(out, k)[off[s]:off[s + 1]], getattr(o1, k)), (s, k)
+
+
+def test_autotuner_picks_a_valid_configuration_and_caches_it(tmp_path, monkeypatch):
+    from paper_2008_11578_amd import autotune, orca
+    monkeypatch.setenv("ORCA_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    sizes = [500, 3000, 64, 1200]
+    parts, prm, off, cat = _batch(sizes, seed=44)
+    st = orca.State.from_arrays(cat)
+    ws = orca.Workspace(st.n, n_scenes=len(sizes))
+    r = autotune.tune_batched(st, off, prm, ws, reps=1)
+    assert r["factor"] in autotune.FACTORS and r["mode"] in autotune.MODES
+    assert r["block"] in autotune.BLOCKS
+    assert r["k_tile"] in autotune.K_TILES and r["k_tile"] >= max(p.max_neighbors for p in prm)
+    assert not r["cached"] and len(r["timings"]) >= len(autotune.FACTORS) + 2
+    r2 = autotune.tune_batched(st, off, prm, ws, reps=1)
+    assert r2["cached"] and r2["block"] == r["block"] and r2["k_tile"] == r["k_tile"]
