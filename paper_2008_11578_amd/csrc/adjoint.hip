@@ -30,7 +30,7 @@
 namespace orca {
 namespace {
 
-constexpr int kAdjBlock = 128;
+constexpr int kAdjBlock = 64;
 constexpr int kBlock = 256;
 constexpr int kEdges = 3;  // at most three lines define an LP result
 

@@ -7,7 +7,7 @@
 namespace orca {
 namespace {
 
-constexpr int kStepBlock = 128;
+constexpr int kStepBlock = 64;  // one wavefront: its LDS is free again as soon as it ends
 
 struct StepArgs {
     orca_agents_in in;
