@@ -170,11 +170,13 @@ def as_dict(sc):
     return {k: getattr(sc, k) for k in oracle._STATE + ("cls",)}
 
 
-def compare_step(state_np, params, *, require_all=False, max_ill_frac=0.01, reps=2):
+def compare_step(state_np, params, *, require_all=False, max_ill_frac=0.01, reps=2, gpu=None):
     """Runs both sides one step from the same FP32 state and asserts the
-    parity contract.  Returns (report, gpu, oracle)."""
+    parity contract.  Returns (report, gpu, oracle).  `gpu` takes a GPU
+    result already computed from this state (px, py, vx, vy, status), for
+    steps launched with a workspace kept across steps."""
     st = as_dict(state_np)
-    g = gpu_step(st, params)
+    g = gpu_step(st, params) if gpu is None else gpu
     o = oracle.step(st, params, want_lines=True)
     dv = np.hypot(g["vx"] - o["vx"], g["vy"] - o["vy"])
     bad = dv > V_TOL

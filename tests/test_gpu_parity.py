@@ -124,6 +124,41 @@ def test_step_dense_crossing_small():
     _print("step crossing 16k t=0", rep)
 
 
+def test_step_c3_full_in_bench_configuration():
+    """The 1,048,576-agent dense crossing with 0.6 m cells, stepped the way
+    the throughput measurement steps it (one workspace kept across steps, so
+    every step after the first narrows its counting pass by the previous
+    K-th neighbour distance): every agent of the steps that open (after 10
+    steps) and close (after 110) the timed window against the oracle."""
+    import dataclasses
+    import torch
+    from paper_2008_11578_amd import orca
+    sc = scenarios.c3_crossing()
+    params = dataclasses.replace(sc.params, cell_size=0.6)
+    state = orca.State.from_arrays(sc)
+    nxt = state.clone()
+    ws = orca.Workspace(state.n)
+    status = torch.zeros(state.n, dtype=torch.uint8, device="cuda")
+    done = 0
+    for target in (10, 110):
+        while done < target:
+            orca.step(state, params, ws, out=nxt, status=status)
+            state, nxt = nxt, state
+            done += 1
+        torch.cuda.synchronize()
+        snap = state.to_numpy()
+        orca.step(state, params, ws, out=nxt, status=status)
+        torch.cuda.synchronize()
+        g = {k: getattr(nxt, k).cpu().numpy() for k in ("px", "py", "vx", "vy")}
+        g["status"] = status.cpu().numpy()
+        rep, _, _ = compare_step(snap, params, gpu=g)
+        _print("step c3 1M after", target, "steps", rep)
+        assert rep["lp3_gpu"] > 0
+        # the step taken for the check continues the run
+        state, nxt = nxt, state
+        done += 1
+
+
 def test_step_deterministic_and_inplace():
     import torch
     from paper_2008_11578_amd import orca
