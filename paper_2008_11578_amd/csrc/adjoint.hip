@@ -200,12 +200,11 @@ __device__ __forceinline__ void adjoint_agent(int s, const AdjArgs &a, const Gri
     float prx = pin_x, pry = pin_y;
     dev::desired_velocity(p, xi, yi, vmax, prx, pry);
     // the goal-mode quantities the desired velocity was formed from
-    float gxg = 0.0f, gyg = 0.0f, d2g = 0.0f, scg = 0.0f;
+    float gxg = 0.0f, gyg = 0.0f, d2g = 0.0f;
     if (p.pref_is_goal) {
         gxg = pin_x - xi;
         gyg = pin_y - yi;
         d2g = gxg * gxg + gyg * gyg;
-        scg = d2g > 0.0f ? fminf(vmax / sqrtf(d2g), p.inv_dt) : 0.0f;
     }
     const dev::LdsLines<BLOCK, ACC> src{lines, tid, nh, cx, cy,
                                         ACC && nh ? dev::accel_half_width(acc, p.dt) : 0.0f};
@@ -583,7 +582,7 @@ __global__ __launch_bounds__(kBlock) void k_tau_partial(const float *__restrict_
     red[threadIdx.x] = s;
     __syncthreads();
     for (int off = kBlock / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
         __syncthreads();
     }
     if (threadIdx.x == 0) blocks[blockIdx.x] = red[0];
@@ -596,7 +595,7 @@ __global__ __launch_bounds__(kTauBlocks) void k_tau_final(const double *__restri
     red[threadIdx.x] = blocks[threadIdx.x];
     __syncthreads();
     for (int off = kTauBlocks / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
         __syncthreads();
     }
     if (threadIdx.x == 0) *g_tau += (float)red[0];

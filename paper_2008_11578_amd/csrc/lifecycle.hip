@@ -448,7 +448,7 @@ __global__ __launch_bounds__(kBlock) void k_overlap_final(const OverlapPart *__r
     sa[threadIdx.x] = a;
     __syncthreads();
     for (int o = kBlock / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) {
+        if ((int)threadIdx.x < o) {
             sg[threadIdx.x] = fmin(sg[threadIdx.x], sg[threadIdx.x + o]);
             sp[threadIdx.x] += sp[threadIdx.x + o];
             sa[threadIdx.x] += sa[threadIdx.x + o];

@@ -213,18 +213,17 @@ struct SortNet {
 };
 
 template <int N>
-__device__ __forceinline__ void cas(uint64_t (&e)[N], int i, int l)
+__device__ __forceinline__ void cas(uint32_t (&e)[N], int i, int l)
 {
-    const uint64_t a = e[i], b = e[l];
-    const bool sw = b < a;
-    e[i] = sw ? b : a;
-    e[l] = sw ? a : b;
+    const uint32_t a = e[i], b = e[l];
+    e[i] = a < b ? a : b;
+    e[l] = a < b ? b : a;
 }
 
 // Batcher's odd-even merge sort (191 comparators for 32 keys against the
 // bitonic network's 240); the loops run at compile time.
 template <int N>
-__device__ __forceinline__ void sort_network(uint64_t (&e)[N])
+__device__ __forceinline__ void sort_network(uint32_t (&e)[N])
 {
 #pragma unroll
     for (int p = 1; p < N; p += p) {
@@ -370,25 +369,45 @@ __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
             });
         }
         // order: a sorting network in registers when the entries fit it,
-        // which orders them by (FP32 key, cell-order position); an FP32-key
-        // tie among the entries that decide the result needs the (FP64 key,
-        // caller index) order of entry_less, left to the insertion pass below
+        // over 32-bit words (the FP32 key in 26-bit fixed point of r2c, above
+        // the entry's buffer slot); the nearest K entries are then gathered
+        // by slot.  The fixed-point key is non-decreasing in the FP32 key,
+        // which is non-decreasing in the FP64 key, so distinct fixed-point
+        // keys are in (FP64 key) order; a tie among the entries that decide
+        // the result needs the (FP64 key, caller index) order of entry_less,
+        // left to the insertion pass below (the buffer is then untouched).
         constexpr int N = SortNet<K>::N;
+        static_assert(N <= 64, "buffer slots must fit six bits");
         bool sorted = false;
         if (take <= (uint32_t)N) {
-            uint64_t e[N];
+            const float qscale = 67108864.0f / (float)r2c;  // 2^26 / r2c
+            uint32_t e[N];
 #pragma unroll
-            for (int p = 0; p < N; ++p) e[p] = p < (int)take ? buf[buf_idx<BLOCK>(p, tid)] : ~0ull;
+            for (int p = 0; p < N; ++p) {
+                uint32_t w = ~0u;
+                if (p < (int)take) {
+                    const float fk = __uint_as_float(
+                        (uint32_t)(buf[buf_idx<BLOCK>(p, tid)] >> 32));
+                    const uint32_t q = (uint32_t)fminf(fk * qscale, 67108863.0f);
+                    w = (q << 6) | (uint32_t)p;
+                }
+                e[p] = w;
+            }
             sort_network<N>(e);
             bool tie = false;
 #pragma unroll
             for (int p = 0; p + 1 < N; ++p)
-                tie = tie || (p < K && p + 1 < (int)take &&
-                              (uint32_t)(e[p] >> 32) == (uint32_t)(e[p + 1] >> 32));
+                tie = tie || (p < K && p + 1 < (int)take && (e[p] >> 6) == (e[p + 1] >> 6));
+            if (!tie) {
+                uint64_t got[K];
 #pragma unroll
-            for (int p = 0; p < N; ++p)
-                if (p < (int)take) buf[buf_idx<BLOCK>(p, tid)] = e[p];
-            sorted = !tie;
+                for (int p = 0; p < K; ++p)
+                    if (p < (int)take) got[p] = buf[buf_idx<BLOCK>((int)(e[p] & 63u), tid)];
+#pragma unroll
+                for (int p = 0; p < K; ++p)
+                    if (p < (int)take) buf[buf_idx<BLOCK>(p, tid)] = got[p];
+                sorted = true;
+            }
         }
         if (!sorted) {
             for (int p = 1; p < (int)take; ++p) {
