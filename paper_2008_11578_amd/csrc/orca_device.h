@@ -304,8 +304,12 @@ __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
                 // used for
                 const int bin = (int)fmin(key * bscale, (double)(kBins - 1));
                 nib += (uint64_t)(in ? 1u : 0u) << (bin * 4);
-                if (in && total < (uint32_t)kCap)
-                    buf[buf_idx<BLOCK>((int)total, tid)] = pack_entry(key, t, (uint32_t)bin);
+                // branch-free, so that the candidates of a group form one
+                // block: every candidate is written at the next free slot and
+                // kept only when in range; once the buffer is full the writes
+                // land on its last slot, the only one they can overwrite
+                const int slot = total < (uint32_t)(kCap - 1) ? (int)total : kCap - 1;
+                buf[buf_idx<BLOCK>(slot, tid)] = pack_entry(key, t, (uint32_t)bin);
                 total += in ? 1u : 0u;
             },
             [&]() {
@@ -318,8 +322,9 @@ __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
         if (total >= (uint32_t)K || !(r2c < g.rn2)) break;
         r2c = g.rn2;  // the guessed circle holds fewer than K: count them all
     }
-    // every candidate of the circle (and the lane's own entry) is in the buffer
-    const bool captured = total + 1u <= (uint32_t)kCap;
+    // every candidate of the circle (and the lane's own entry) is in the
+    // buffer, below its last slot
+    const bool captured = total + 1u <= (uint32_t)(kCap - 1);
 
     // threshold bin b*: the first bin at which the cumulative count reaches K
     uint32_t cum = 0, take = 0;
