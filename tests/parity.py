@@ -173,8 +173,8 @@ def as_dict(sc):
 def compare_step(state_np, params, *, require_all=False, max_ill_frac=0.01, reps=2, gpu=None):
     """Runs both sides one step from the same FP32 state and asserts the
     parity contract.  Returns (report, gpu, oracle).  `gpu` takes a GPU
-    result already computed from this state (px, py, vx, vy, status), for
-    steps launched with a workspace kept across steps."""
+    result already computed from this state (px, py, vx, vy, status): a step
+    launched with a workspace kept across steps, or a scene of a batch."""
     st = as_dict(state_np)
     g = gpu_step(st, params) if gpu is None else gpu
     o = oracle.step(st, params, want_lines=True)

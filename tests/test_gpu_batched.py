@@ -90,6 +90,59 @@ def test_batched_c4_shape_runs_and_flags_nothing():
         assert np.mean(dv > V_TOL) < 0.01
 
 
+@pytest.mark.parametrize("block", [64, 256])
+def test_batched_c4_full_in_measured_configuration(block):
+    """All 512 scenes (5,559,168 agents) of the batched workload, in the launch
+    configurations the autotuner chooses between at this size (cells of
+    R_n / 2, the persistent form, capacity 16): every agent against the
+    oracle, every scene bit for bit against its own plain step, and the full
+    parity contract on the largest scenes and a few small ones."""
+    import torch
+    from paper_2008_11578_amd import orca
+    sc = scenarios.c4_batched()
+    S = len(sc.scene_params)
+    prm = [dataclasses.replace(p, cell_size=0.5 * p.neighbor_dist) for p in sc.scene_params]
+    st = orca.State.from_arrays(sc)
+    b = orca.Batch(sc.scene_off, prm, mode=0, block=block, k_tile=16)
+    status = torch.zeros(st.n, dtype=torch.uint8, device="cuda")
+    out = orca.step_batched(st, b, orca.Workspace(st.n, n_scenes=S), status=status)
+    torch.cuda.synchronize()
+    assert int(b.error.item()) == 0
+    g = {k: getattr(out, k).cpu().numpy() for k in ("px", "py", "vx", "vy")}
+    g["status"] = status.cpu().numpy()
+    print("c4 full", S, "scenes", st.n, "agents, block", block, flush=True)
+
+    # every agent against the oracle's batched step
+    cat = as_dict(sc)
+    ob = oracle.step_batched(cat, sc.scene_off, prm)
+    dv = np.hypot(g["vx"] - ob["vx"], g["vy"] - ob["vy"])
+    print("  oracle: max dv", float(dv.max()), "over tolerance", int(np.sum(dv > V_TOL)),
+          flush=True)
+    assert np.mean(dv > V_TOL) < 1e-5
+
+    # every scene equals its plain step
+    for s in range(S):
+        a, z = int(sc.scene_off[s]), int(sc.scene_off[s + 1])
+        sp = orca.State(**{k: getattr(st, k)[a:z] for k in orca.STATE_FIELDS})
+        st1 = torch.zeros(z - a, dtype=torch.uint8, device="cuda")
+        o1 = orca.step(sp, prm[s], orca.Workspace(z - a), status=st1)
+        torch.cuda.synchronize()
+        for k in ("px", "py", "vx", "vy"):
+            assert torch.equal(getattr(out, k)[a:z], getattr(o1, k)), (s, k)
+        assert torch.equal(status[a:z], st1), s
+
+    # the full contract (conditioning, valid answers) on a sample of scenes
+    # and on every scene that holds an agent outside the tolerance
+    sizes = np.diff(sc.scene_off)
+    outside = np.searchsorted(sc.scene_off, np.nonzero(dv > V_TOL)[0], side="right") - 1
+    sample = sorted(set(np.argsort(sizes)[-3:].tolist() + [0, S // 2, S - 1] + outside.tolist()))
+    for s in sample:
+        a, z = int(sc.scene_off[s]), int(sc.scene_off[s + 1])
+        part = {k: v[a:z] for k, v in cat.items()}
+        rep, _, _ = compare_step(part, prm[s], gpu={k: v[a:z] for k, v in g.items()})
+        print("  scene", int(s), rep, flush=True)
+
+
 def test_batched_error_flag_on_bad_offsets():
     import torch
     from paper_2008_11578_amd import orca
