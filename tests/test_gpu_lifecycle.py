@@ -173,3 +173,66 @@ def test_crossing_run_conserves_agents(kind):
     assert sum(row["arrived"] for row in r["rows"]) == r["arrived"]
     print(kind, r["steps"], "steps; lp3 share", round(r["lp3_share"], 4), "max overlap pairs",
           r["max_overlap_pairs"], "min clearance", r["min_clearance"])
+
+
+def test_extensions_full_size_measured_configuration():
+    """The three calls as the throughput measurement makes them on the
+    1,048,576-agent dense crossing: removal with one agent in ten on its goal,
+    16,384 spawn candidates uniform over the 700 m square with a 1 s window,
+    and the overlap statistics within 1 m; decisions, counts and written
+    agents against the oracle, bit for bit."""
+    import torch
+    from paper_2008_11578_amd import orca, scenarios
+    sc = scenarios.c3_crossing()
+    n = sc.n
+    rng = np.random.default_rng(17)
+    arr = dict(sc.arrays())
+    done = rng.random(n) < 0.1
+    arr["pref_x"] = np.where(done, arr["px"], arr["pref_x"]).astype(F32)
+    arr["pref_y"] = np.where(done, arr["py"], arr["pref_y"]).astype(F32)
+    st = orca.State.from_arrays(arr)
+    out = st.clone()
+    o2n = torch.empty(n, dtype=torch.int32, device="cuda")
+    lws = orca.LifecycleWorkspace(n, orca.SPAWN_MAX)
+    kept = int(orca.remove_arrived(st, out, lws, old_to_new=o2n).item())
+    ref = oracle.remove_arrived(arr)
+    print("remove: kept", kept, "of", n, flush=True)
+    assert kept == ref["px"].shape[0]
+    for k in FIELDS:
+        np.testing.assert_array_equal(getattr(out, k)[:kept].cpu().numpy(), ref[k])
+    np.testing.assert_array_equal(o2n.cpu().numpy(), ref["old_to_new"])
+
+    nc = orca.SPAWN_MAX
+    side = 700.0
+    cand = {k: np.zeros(nc, F32) for k in FIELDS if k != "cls"}
+    cand["px"] = rng.uniform(0, side, nc).astype(F32)
+    cand["py"] = rng.uniform(0, side, nc).astype(F32)
+    cand["pref_x"] = rng.uniform(0, side, nc).astype(F32)
+    cand["pref_y"] = rng.uniform(0, side, nc).astype(F32)
+    cand["radius"] = np.full(nc, 0.3, F32)
+    cand["max_speed"] = np.full(nc, 1.5, F32)
+    cand["cls"] = np.zeros(nc, np.uint8)
+    big = orca.State(**{k: torch.cat([getattr(st, k), torch.zeros(nc, dtype=getattr(st, k).dtype,
+                                                                  device="cuda")])
+                        for k in orca.STATE_FIELDS})
+    acc = torch.empty(nc, dtype=torch.uint8, device="cuda")
+    tot = int(orca.spawn(big, n, orca.State.from_arrays(cand), 1.0, lws, accepted=acc).item())
+    ref_acc = oracle.spawn(arr, cand, 1.0)
+    print("spawn: accepted", tot - n, "of", nc, flush=True)
+    np.testing.assert_array_equal(acc.cpu().numpy(), ref_acc)
+    assert tot == n + int(ref_acc.sum())
+    keep = ref_acc.astype(bool)
+    for k in FIELDS:
+        np.testing.assert_array_equal(getattr(big, k)[n:tot].cpu().numpy(), cand[k][keep])
+
+    # as measured, and with radii grown by 1.6 so that many pairs overlap
+    grown = dict(arr)
+    grown["radius"] = (arr["radius"] * F32(1.6)).astype(F32)
+    for a in (arr, grown):
+        got = orca.overlap_stats(orca.State.from_arrays(a), 1.0,
+                                 orca.OverlapWorkspace(n)).cpu().numpy()
+        ref = oracle.overlap_stats_tree(a, 1.0)
+        print("overlap:", got.tolist(), ref, flush=True)
+        assert int(got[0]) == ref["pairs"] and int(got[1]) == ref["agents"]
+        assert abs(got[2] - ref["min_clearance"]) <= 1e-12
+    assert ref["pairs"] > 0

@@ -106,3 +106,55 @@ def test_spawn_is_greedy_and_maximal(oracle_mod):
                              cand["max_speed"][earlier]).any()
         assert acc[c] == (not blocked_agent and not blocked_cand), c
     assert 0 < acc.sum() < nc
+
+
+def test_overlap_stats_closed_forms(oracle_mod):
+    """Two discs at distance d (exact binary values): one overlapping pair
+    exactly when d < r_1 + r_2 (touching is not overlapping), clearance
+    d - (r_1 + r_2); pairs beyond the reach count for nothing; fewer than two
+    agents give no pair and an infinite clearance."""
+    for f in (oracle_mod.overlap_stats, oracle_mod.overlap_stats_tree):
+        for d, pairs in ((0.5, 1), (0.75, 0), (1.0, 0)):
+            st = _agents([0.0, d], [0.0, 0.0])
+            st["radius"] = np.array([0.25, 0.5], F32)
+            got = f(st, 2.0)
+            assert got["pairs"] == pairs and got["agents"] == 2 * pairs
+            assert got["min_clearance"] == d - 0.75
+        # a third agent 3 m away is outside a 2 m reach
+        st = _agents([0.0, 1.0, 4.0], [0.0, 0.0, 0.0])
+        st["radius"] = np.array([0.25, 0.5, 0.25], F32)
+        got = f(st, 2.0)
+        assert got["pairs"] == 0 and got["min_clearance"] == 0.25
+        for m in (0, 1):
+            got = f(_agents([0.0] * m, [0.0] * m), 2.0)
+            assert got["pairs"] == 0 and got["agents"] == 0 and np.isinf(got["min_clearance"])
+
+
+def test_overlap_stats_lattice(oracle_mod):
+    """k x k lattice of spacing 1 m, radius 0.625 m: lattice neighbours
+    overlap (1.25 > 1), diagonal ones do not (1.25 < sqrt 2), so there are
+    2 k (k - 1) pairs, every agent is in one, and the clearance is -0.25."""
+    k = 30
+    gx, gy = np.meshgrid(np.arange(k, dtype=F32), np.arange(k, dtype=F32))
+    st = _agents(gx.ravel(), gy.ravel(), r=0.625)
+    for f in (oracle_mod.overlap_stats, oracle_mod.overlap_stats_tree):
+        got = f(st, 3.0)
+        assert got["pairs"] == 2 * k * (k - 1)
+        assert got["agents"] == k * k
+        assert got["min_clearance"] == -0.25
+
+
+def test_overlap_stats_tree_equals_all_pairs(oracle_mod):
+    """The k-d tree listing and the all-pairs loop agree exactly on random
+    crowds with mixed radii, including pairs at the reach boundary."""
+    rng = np.random.default_rng(5)
+    for n, side, reach in ((2000, 40.0, 3.0), (3000, 25.0, 1.0), (500, 5.0, 0.5)):
+        st = _agents(rng.uniform(0, side, n), rng.uniform(0, side, n))
+        st["radius"] = np.where(rng.random(n) < 0.1, 1.5, 0.3).astype(F32)
+        # a pair exactly at the reach (not counted) and one just inside it
+        st["px"][:4] = np.array([0.0, reach, 100.0, 100.0 + np.nextafter(F32(reach), F32(0))], F32)
+        st["py"][:4] = np.array([-50.0, -50.0, -50.0, -50.0], F32)
+        a = oracle_mod.overlap_stats(st, reach)
+        b = oracle_mod.overlap_stats_tree(st, reach)
+        assert a == b
+        assert a["pairs"] > 0
