@@ -37,6 +37,32 @@ def test_capped_step_matches_oracle(accel, k):
     assert moved.sum() > 50
 
 
+def test_capped_step_full_size_measured_configuration():
+    """The 1,048,576-agent dense crossing with caps of 2 m/s^2 for both
+    classes, 0.6 m cells, one workspace kept across steps, as the
+    throughput measurement steps it: every agent of the sixth step against
+    the oracle."""
+    import torch
+    from paper_2008_11578_amd import orca
+    sc = scenarios.c3_crossing()
+    params = dataclasses.replace(sc.params, cell_size=0.6, accel=(2.0, 2.0))
+    state = orca.State.from_arrays(sc)
+    nxt = state.clone()
+    ws = orca.Workspace(state.n)
+    status = torch.zeros(state.n, dtype=torch.uint8, device="cuda")
+    for _ in range(5):
+        orca.step(state, params, ws, out=nxt, status=status)
+        state, nxt = nxt, state
+    torch.cuda.synchronize()
+    snap = state.to_numpy()
+    orca.step(state, params, ws, out=nxt, status=status)
+    torch.cuda.synchronize()
+    g = {k: getattr(nxt, k).cpu().numpy() for k in ("px", "py", "vx", "vy")}
+    g["status"] = status.cpu().numpy()
+    rep, _, _ = compare_step(snap, params, gpu=g)
+    _print("capped c3 1M", rep)
+
+
 def test_capped_step_every_velocity_within_its_octagon():
     """GPU velocities respect the acceleration lines the oracle forms for
     each agent (to FP32 rounding)."""
