@@ -344,14 +344,15 @@ __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
     if (total <= 255u && take <= (uint32_t)kCap) {
         if (captured) {
             // the candidates of bins <= b* are already in the buffer: keep
-            // them in place, dropping the lane's own entry
+            // them in place, dropping the lane's own entry.  Branch-free: each
+            // entry is written at the next kept position, which never passes
+            // the one being read, and the position advances only for kept
+            // entries
             uint32_t w = 0;
             for (uint32_t e = 0; e <= total; ++e) {
                 const uint64_t ent = buf[buf_idx<BLOCK>((int)e, tid)];
-                if (entry_pos(ent) != spos && (int)entry_bin(ent) <= bstar) {
-                    buf[buf_idx<BLOCK>((int)w, tid)] = ent;
-                    ++w;
-                }
+                buf[buf_idx<BLOCK>((int)w, tid)] = ent;
+                w += (entry_pos(ent) != spos && (int)entry_bin(ent) <= bstar) ? 1u : 0u;
             }
         } else {
             // pass 2: collect the candidates of bins <= b*, in scan order.  For
