@@ -161,6 +161,32 @@ def test_step_c3_full_in_bench_configuration():
         done += 1
 
 
+def test_kept_distances_change_no_result_full_size():
+    """The measured 1M crossing stepped with a workspace kept across steps
+    (counting pass narrowed by the previous K-th neighbour distances) equals,
+    bit for bit, a step from the same state with a fresh workspace (whole
+    neighbour circle), at states spread over the measured window."""
+    import dataclasses
+    import torch
+    from paper_2008_11578_amd import orca
+    sc = scenarios.c3_crossing()
+    params = dataclasses.replace(sc.params, cell_size=0.6)
+    state = orca.State.from_arrays(sc)
+    nxt = state.clone()
+    fresh = state.clone()
+    ws = orca.Workspace(state.n)
+    checks = (10, 27, 28, 60, 109)
+    for t in range(110):
+        if t in checks:
+            orca.step(state, params, orca.Workspace(state.n), out=fresh)
+        orca.step(state, params, ws, out=nxt)
+        if t in checks:
+            torch.cuda.synchronize()
+            for k in ("px", "py", "vx", "vy"):
+                assert torch.equal(getattr(nxt, k), getattr(fresh, k)), (t, k)
+        state, nxt = nxt, state
+
+
 def test_step_deterministic_and_inplace():
     import torch
     from paper_2008_11578_amd import orca
