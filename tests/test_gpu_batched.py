@@ -143,6 +143,33 @@ def test_batched_c4_full_in_measured_configuration(block):
         print("  scene", int(s), rep, flush=True)
 
 
+def test_batched_kept_distances_change_no_result_full_size():
+    """All 512 scenes stepped 30 times with a workspace kept across steps (as
+    the measured graph does) equal, bit for bit, batched steps from the same
+    states with a fresh workspace, at several of those steps."""
+    import torch
+    from paper_2008_11578_amd import orca
+    sc = scenarios.c4_batched()
+    S = len(sc.scene_params)
+    prm = [dataclasses.replace(p, cell_size=0.5 * p.neighbor_dist) for p in sc.scene_params]
+    b = orca.Batch(sc.scene_off, prm, mode=0, block=64, k_tile=16)
+    state = orca.State.from_arrays(sc)
+    nxt = state.clone()
+    fresh = state.clone()
+    ws = orca.Workspace(state.n, n_scenes=S)
+    checks = (1, 5, 15, 29)
+    for t in range(30):
+        if t in checks:
+            orca.step_batched(state, b, orca.Workspace(state.n, n_scenes=S), out=fresh)
+        orca.step_batched(state, b, ws, out=nxt)
+        if t in checks:
+            torch.cuda.synchronize()
+            assert int(b.error.item()) == 0
+            for k in ("px", "py", "vx", "vy"):
+                assert torch.equal(getattr(nxt, k), getattr(fresh, k)), (t, k)
+        state, nxt = nxt, state
+
+
 def test_batched_error_flag_on_bad_offsets():
     import torch
     from paper_2008_11578_amd import orca
