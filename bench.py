@@ -47,17 +47,29 @@ OP_COST = (10, 0, 65, 4, 20, 15, 0, 10, 20, 4, 20, 15)
 # px, py, vx, vy, radius (cell-ordered copy), pref_x, pref_y, max_speed, class
 # (33 B), write px, py, vx, vy (16 B).
 STEP_BYTES_PER_AGENT = 49
+# Algorithmic HBM bytes per agent-step of the adjoint kernel: the forward
+# recomputation's 33 B read, the cotangents of (p', v') read (16 B), the
+# cotangents of (p, v) and of pref written (24 B), the tau term (4 B), and
+# three neighbour edges of 20 B written (60 B).
+ADJ_BYTES_PER_AGENT = 33 + 16 + 24 + 4 + 60
+# Algorithmic VALU lane-ops of the adjoint beyond its forward recomputation:
+# the VJP of every half-plane through its frozen branch (twice the forward
+# half-plane, 2 x 65) and the VJP of the LP's active set (a 2x2 solve and its
+# transpose, 40 per agent).
+ADJ_OPS_PER_NEIGHBOR = 130
+ADJ_OPS_PER_AGENT = 40
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def source_hash() -> str:
-    """Hash of the step kernel's source (comments removed, so that only a
-    change of code invalidates the committed counter summaries)."""
+def source_hash(files=("step.hip", "orca_device.h", "orca_internal.h")) -> str:
+    """Hash of a kernel's source files (comments removed, so that only a
+    change of code invalidates the committed counter summaries); by default
+    the step kernel's."""
     h = hashlib.sha256()
-    for f in ("step.hip", "orca_device.h", "orca_internal.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2008_11578_amd", "csrc", f)) as fh:
             code = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
         code = re.sub(r"//[^\n]*", "", code)
@@ -76,7 +88,16 @@ def traffic_from_profile(kernel_hash: str):
     mb = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
     if not mh or not mb or mh.group(1) != kernel_hash:
         return None
-    return float(mb.group(1))
+
+    def num(key):
+        m = re.search(key + r":\s*([0-9.eE+]+)", txt)
+        return float(m.group(1)) if m else None
+
+    # raw counters beside the calibrated bytes: the scale comes from a plain
+    # streaming copy, which need not hold for the step's 16-byte gathers
+    return {"bytes": float(mb.group(1)), "fetch_kib": num("fetch_kib_per_launch"),
+            "write_kib": num("write_kib_per_launch"),
+            "scale": {"fetch": num("fetch_scale"), "write": num("write_scale")}}
 
 
 def valu_from_profile(kernel_hash: str):
@@ -153,7 +174,7 @@ def cpu_baseline(state_start, state_end, params, n, steps, steps_1t=2):
     import numpy as np
     import oracle
     oracle.build(force=False)
-    threads = oracle.set_threads(0)
+    threads = oracle.set_threads(oracle_threads())
     t0 = time.perf_counter()
     st = dict(state_start)
     w_start = None
@@ -184,6 +205,181 @@ def cpu_baseline(state_start, state_end, params, n, steps, steps_1t=2):
     return rate, elapsed, threads, w_start, o_end["work"], rate_1t
 
 
+def oracle_ops(states, params):
+    """Average algorithmic lane-ops per step launch over the given states
+    (the oracle's work counters x OP_COST), with the mean in-range neighbour
+    count and the LP3 share."""
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    ops, nb, lp3 = [], [], []
+    for st in states:
+        w = oracle.step(st, params, want_work=True)["work"]
+        ops.append(algorithmic_ops(w))
+        nb.append(float(w[:, 2].mean()))
+        lp3.append(float(w[:, 6].mean()))
+    return float(np.mean(ops)), float(np.mean(nb)), float(np.mean(lp3))
+
+
+def oracle_rate(state0, params, n, steps, threads=0):
+    """The FP64 oracle stepped `steps` times from state0 (each step's FP32
+    rounding fed back, as the GPU state is) on `threads` host threads (0:
+    all); returns (agent-steps/s, seconds, threads used)."""
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    full = oracle_threads()
+    used = oracle.set_threads(threads if threads > 0 else full)
+    try:
+        st = dict(state0)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            o = oracle.step(st, params)
+            st = dict(st)
+            for k in ("px", "py", "vx", "vy"):
+                st[k] = o[k].astype(np.float32)
+        el = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(full)
+    return n * steps / el, el, used
+
+
+_FULL_THREADS = []
+
+
+def oracle_threads() -> int:
+    """The oracle's default (all host threads) OpenMP thread count."""
+    if not _FULL_THREADS:
+        import oracle
+        _FULL_THREADS.append(oracle.set_threads(0))
+    return _FULL_THREADS[0]
+
+
+def alu_roofline(ops, k_ms, n, bytes_per_agent, kernel, **extra):
+    """Roofline object of a step-type kernel: algorithmic lane-ops per launch
+    over its measured duration against the vector-ALU peak, with the
+    algorithmic HBM rate against the HBM peak beside it."""
+    achieved = ops / (k_ms * 1e-3) / 1e12
+    hbm = bytes_per_agent * n / (k_ms * 1e-3) / 1e9
+    out = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Top/s",
+           "frac": achieved / VALU_PEAK_TOPS, "traffic": None, "kernel": kernel,
+           "kernel_ms": k_ms, "ops_per_launch": ops,
+           "hbm_algorithmic_GBs": hbm, "hbm_frac": hbm / HBM_PEAK_GBS,
+           "hbm_peak_GBs": HBM_PEAK_GBS}
+    out.update(extra)
+    return out
+
+
+def run_plain(sc, params, steps, warmup):
+    """Steps one scene `warmup` + `steps` times through orca_step_ex on one
+    workspace kept across steps (HIP events around the grid build and the
+    step kernel of every timed step).  Returns the wall time, the mean event
+    times, the LP3 share of the last step and the states opening and closing
+    the timed window."""
+    import numpy as np
+    import torch
+    from paper_2008_11578_amd import orca
+    n = sc.n
+    state = orca.State.from_arrays(sc)
+    nxt = state.clone()
+    ws = orca.Workspace(n)
+    status = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    for _ in range(warmup):
+        orca.step(state, params, ws, out=nxt, status=status)
+        state, nxt = nxt, state
+    torch.cuda.synchronize()
+    out = {"start": state.to_numpy()}
+    hip = HipEvents()
+    # events are created before the timed region
+    pre = [(hip.create(), hip.create(), hip.create()) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        orca.step(state, params, ws, out=nxt, status=status, events=pre[s])
+        state, nxt = nxt, state
+    torch.cuda.synchronize()
+    out["wall"] = time.perf_counter() - t0
+    out["grid_ms"] = float(np.mean([hip.elapsed_ms(a, b) for a, b, c in pre]))
+    out["k_ms"] = float(np.mean([hip.elapsed_ms(b, c) for a, b, c in pre]))
+    hip.close()
+    out["lp3_share"] = float(status.float().mean().item())
+    out["end"] = state.to_numpy()
+    return out
+
+
+def bench_config_leg(name, sc, params, steps, cpu_1t_steps, cpu=True):
+    """One plain configuration run for its whole step count from its seeded
+    initial state (after an untimed warm-up run on a copy), with the step
+    kernel's roofline and the oracle timed on the same step count."""
+    from paper_2008_11578_amd import orca
+    n = sc.n
+    warm = run_plain(sc, params, min(steps, 5), 0)  # code objects, caches
+    del warm
+    r = run_plain(sc, params, steps, 0)
+    value = n * steps / r["wall"]
+    leg = {"workload": sc.name, "agents": n, "steps": steps, "value": value,
+           "unit": "agent-steps/s", "ms_per_step": r["wall"] * 1e3 / steps,
+           "grid_ms": r["grid_ms"], "step_kernel_ms": r["k_ms"], "lp3_share_end": r["lp3_share"]}
+    if cpu:
+        ops, nbr, lp3 = oracle_ops([r["start"], r["end"]], params)
+        leg["roofline"] = alu_roofline(ops, r["k_ms"], n, STEP_BYTES_PER_AGENT,
+                                       f"k_step<{params.max_neighbors}>",
+                                       mean_neighbors=nbr, oracle_lp3_share=lp3)
+        rate, el, th = oracle_rate(r["start"], params, n, steps)
+        rate1, el1, _ = oracle_rate(r["start"], params, n, cpu_1t_steps, threads=1)
+        leg["cpu_baseline"] = {
+            "value": rate, "unit": "agent-steps/s", "cores": th, "kind": "oracle",
+            "sample": f"the whole {steps}-step run from the same initial state ({el:.2f} s); "
+                      f"single thread: {cpu_1t_steps} steps ({el1:.2f} s)",
+            "single_thread_value": rate1, "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+            "speedup": value / rate}
+    log(f"[bench] {name}: {n} agents x {steps} steps, {leg['ms_per_step']:.3f} ms/step, "
+        f"step kernel {r['k_ms']:.3f} ms, {value:.3e} agent-steps/s"
+        + (f", oracle {leg['cpu_baseline']['value']:.3e} ({leg['cpu_baseline']['cores']} threads),"
+           f" roofline frac {leg['roofline']['frac']:.3f}" if cpu else ""))
+    return leg
+
+
+def grid_kernels_from_profile(n, n_cells, grid_ms):
+    """HBM fractions of the grid-build kernels of the measured workload:
+    algorithmic bytes per launch (n agents, n_cells cells) over each
+    kernel's average duration from the committed rocprofv3 kernel trace of
+    the same command, while the grid source is the one it was taken on; and
+    the whole build's bytes over the live HIP-event time of the build."""
+    per_kernel = {
+        # read px, py; clear the histogram
+        "k_bbox_partial": 8 * n + 4 * n_cells,
+        # read px, py; write cell and rank; histogram counts read and written
+        "k_cell_count": 16 * n + 8 * n_cells,
+        # read the histogram
+        "k_scan_reduce": 4 * n_cells,
+        # read the histogram, write the cell starts
+        "k_scan_apply": 8 * n_cells,
+        # read cell, rank, start[cell], px, py, radius, vx, vy, class; write two float4
+        "k_scatter": 33 * n + 32 * n,
+    }
+    total = sum(per_kernel.values())
+    out = {"algorithmic_bytes": total, "grid_ms": grid_ms,
+           "hbm_frac_whole_build": total / (grid_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "cells": n_cells, "kernels": None}
+    path = os.path.join(ROOT, "profiles", "k_step_c3_1M_kernel_stats.md")
+    if not os.path.exists(path):
+        return out
+    txt = open(path).read()
+    mh = re.search(r"grid_source_hash:\s*([0-9a-f]+)", txt)
+    if not mh or mh.group(1) != source_hash(("grid.hip", "orca_internal.h")):
+        return out
+    ks = {}
+    for name, b in per_kernel.items():
+        m = re.search(r"\|\s*" + name + r"\s*\|\s*(\d+)\s*\|\s*([0-9.]+)\s*\|", txt)
+        if m:
+            us = float(m.group(2))
+            ks[name] = {"bytes": b, "avg_us": us, "GBs": b / (us * 1e-6) / 1e9,
+                        "hbm_frac": b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS}
+    out["kernels"] = ks
+    return out
+
+
 def capture_loop(step_fn, a, b, steps):
     """Records `steps` ping-pong steps a->b->a... into one HIP graph; returns
     (graph, final state)."""
@@ -201,10 +397,14 @@ def capture_loop(step_fn, a, b, steps):
     return graph, x
 
 
-def bench_batched(steps: int):
+def bench_batched(steps: int, cpu: bool = True):
     """512 uneven scenes (about 5.6M agents) per step: the autotuned batched
     step captured as a `steps`-step graph, against 512 sequential single-scene
-    steps captured as a graph."""
+    steps captured as a graph.  The persistent step kernel's duration comes
+    from HIP events around it over eager steps after the graph; its roofline
+    takes the oracle's work counters on the states opening and closing the
+    timed graph; the oracle's batched step is timed beside it."""
+    import numpy as np
     import torch
     from paper_2008_11578_amd import autotune, orca, scenarios
     sc = scenarios.c4_batched()
@@ -219,11 +419,25 @@ def bench_batched(steps: int):
     graph, _ = capture_loop(lambda x, y: orca.step_batched(x, batch, ws, out=y), st, nxt, steps)
     graph.replay()
     torch.cuda.synchronize()
+    snap_start = st.to_numpy() if cpu else None
     t0 = time.perf_counter()
     graph.replay()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
+    snap_end = st.to_numpy() if cpu else None
     assert int(batch.error.item()) == 0
+    # the step kernel alone: HIP events around it over eager steps
+    hip = HipEvents()
+    k_steps = 10
+    pre = [(hip.create(), hip.create(), hip.create()) for _ in range(k_steps)]
+    a, b = st, nxt
+    for e in pre:
+        orca.step_batched(a, batch, ws, out=b, events=e)
+        a, b = b, a
+    torch.cuda.synchronize()
+    k_ms = float(np.mean([hip.elapsed_ms(e[1], e[2]) for e in pre]))
+    g_ms = float(np.mean([hip.elapsed_ms(e[0], e[1]) for e in pre]))
+    hip.close()
     # per-scene baseline: one orca_step per scene, sequentially, in a graph
     parts = []
     for s in range(S):
@@ -256,43 +470,96 @@ def bench_batched(steps: int):
     torch.cuda.synchronize()
     ms_ps = (time.perf_counter() - t0) * 1e3 / 2
     log(f"[bench] batched {S} scenes, {n} agents: {ms:.3f} ms/step (graph of {steps}), "
-        f"per-scene {ms_ps:.3f} ms/step, tuned factor {tuned['factor']:.3f} mode {tuned['mode']} "
-        f"block {tuned['block']} k tile {tuned['k_tile']}")
-    return {"metric": "scene-steps/s (512 uneven scenes, one batched step per graph node set)",
-            "scenes": S, "agents": n, "ms_per_step": ms,
-            "scene_steps_per_s": S / (ms * 1e-3), "agent_steps_per_s": n / (ms * 1e-3),
-            "per_scene_ms_per_step": ms_ps, "speedup_vs_per_scene": ms_ps / ms,
-            "graph_steps": steps, "tuned": {"cell_factor": tuned["factor"],
-                                             "mode": tuned["mode"], "block": tuned["block"],
-                                             "k_tile": tuned["k_tile"]}}
+        f"step kernel {k_ms:.3f} ms, per-scene {ms_ps:.3f} ms/step, tuned factor "
+        f"{tuned['factor']:.3f} mode {tuned['mode']} block {tuned['block']} "
+        f"k tile {tuned['k_tile']}")
+    out = {"metric": "scene-steps/s (512 uneven scenes, one batched step per graph node set)",
+           "scenes": S, "agents": n, "ms_per_step": ms,
+           "scene_steps_per_s": S / (ms * 1e-3), "agent_steps_per_s": n / (ms * 1e-3),
+           "grid_ms": g_ms, "step_kernel_ms": k_ms,
+           "per_scene_ms_per_step": ms_ps, "speedup_vs_per_scene": ms_ps / ms,
+           "graph_steps": steps, "tuned": {"cell_factor": tuned["factor"],
+                                            "mode": tuned["mode"], "block": tuned["block"],
+                                            "k_tile": tuned["k_tile"]}}
+    if cpu:
+        import oracle
+        oracle.build(force=False)
+        prm = tuned["params"]
+        ops = []
+        for snap in (snap_start, snap_end):
+            w = oracle.step_batched(snap, sc.scene_off, prm, want_work=True)["work"]
+            ops.append(algorithmic_ops(w))
+        k_max = max(p.max_neighbors for p in prm)
+        out["roofline"] = alu_roofline(float(np.mean(ops)), k_ms, n, STEP_BYTES_PER_AGENT,
+                                       f"k_step_batched<{tuned['k_tile'] or k_max}>")
+        full = oracle_threads()
+        oracle.set_threads(full)
+        reps = 3
+        t0 = time.perf_counter()
+        cur = dict(snap_start)
+        for _ in range(reps):
+            o = oracle.step_batched(cur, sc.scene_off, prm)
+            cur = dict(cur)
+            for k in ("px", "py", "vx", "vy"):
+                cur[k] = o[k].astype(np.float32)
+        el = time.perf_counter() - t0
+        # one thread: one step of the first 128 scenes (a bounded sample)
+        s1 = 128
+        n1 = int(sc.scene_off[s1])
+        part = {k: v[:n1] for k, v in snap_start.items()}
+        oracle.set_threads(1)
+        try:
+            t1 = time.perf_counter()
+            oracle.step_batched(part, sc.scene_off[:s1 + 1], prm[:s1])
+            el1 = time.perf_counter() - t1
+        finally:
+            oracle.set_threads(full)
+        rate = n * reps / el
+        out["cpu_baseline"] = {
+            "value": rate, "unit": "agent-steps/s", "cores": full, "kind": "oracle",
+            "sample": f"{reps} batched oracle steps of all {S} scenes from the state opening the "
+                      f"timed graph ({el:.1f} s); single thread: one step of the first {s1} "
+                      f"scenes ({n1} agents, {el1:.2f} s)",
+            "single_thread_value": n1 / el1, "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+            "speedup": (n / (ms * 1e-3)) / rate}
+        log(f"[bench] batched oracle {rate:.3e} agent-steps/s on {full} threads; roofline frac "
+            f"{out['roofline']['frac']:.3f}")
+    return out
 
 
-def bench_vehicle_share(steps: int = 100, warmup: int = 10):
+def bench_vehicle_share(steps: int = 100, warmup: int = 10, cpu: bool = True):
     """Agent-steps/s of the mixed-crowd geometry (66,560 agents) at vehicle
     shares 0, 1.5, 5 and 50 %: pedestrians and vehicles take the same
-    instructions, so the rate should not depend on the share."""
-    import torch
-    from paper_2008_11578_amd import orca, scenarios
-    rates = {}
+    instructions, so the rate per unit of work should not depend on the
+    share.  Per share: the step kernel's time (HIP events), the oracle's
+    algorithmic lane-ops per launch on the states opening and closing the
+    timed steps, and the lane-ops per second this gives."""
+    from paper_2008_11578_amd import scenarios
+    rates, per = {}, {}
     for share in (0.0, 0.015, 0.05, 0.5):
         sc = scenarios.c2_vehicle_share(share)
-        st = orca.State.from_arrays(sc)
-        nxt = st.clone()
-        ws = orca.Workspace(sc.n)
-        for _ in range(warmup):
-            orca.step(st, sc.params, ws, out=nxt)
-            st, nxt = nxt, st
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            orca.step(st, sc.params, ws, out=nxt)
-            st, nxt = nxt, st
-        torch.cuda.synchronize()
-        rates[f"{share:g}"] = sc.n * steps / (time.perf_counter() - t0)
+        r = run_plain(sc, sc.params, steps, warmup)
+        key = f"{share:g}"
+        rates[key] = sc.n * steps / r["wall"]
+        d = {"agent_steps_per_s": rates[key], "step_kernel_ms": r["k_ms"],
+             "lp3_share_end": r["lp3_share"]}
+        if cpu:
+            ops, nbr, lp3 = oracle_ops([r["start"], r["end"]], sc.params)
+            d.update(ops_per_agent_step=ops / sc.n, oracle_lp3_share=lp3,
+                     lane_ops_Tps=ops / (r["k_ms"] * 1e-3) / 1e12,
+                     frac=ops / (r["k_ms"] * 1e-3) / 1e12 / VALU_PEAK_TOPS)
+        per[key] = d
     lo, hi = min(rates.values()), max(rates.values())
-    log("[bench] vehicle share " + ", ".join(f"{k}: {v:.3e}" for k, v in rates.items()))
-    return {"metric": "agent-steps/s, 66,560 agents, by vehicle share", "steps": steps,
-            "rates": rates, "spread": hi / lo - 1.0}
+    out = {"metric": "agent-steps/s, 66,560 agents, by vehicle share", "steps": steps,
+           "rates": rates, "spread": hi / lo - 1.0, "per_share": per}
+    if cpu:
+        f = [d["lane_ops_Tps"] for d in per.values()]
+        out["work_rate_spread"] = max(f) / min(f) - 1.0
+    log("[bench] vehicle share " + ", ".join(
+        f"{k}: {v['agent_steps_per_s']:.3e} agent-steps/s"
+        + (f" ({v['ops_per_agent_step']:.0f} ops/agent-step, {v['lane_ops_Tps']:.2f} Top/s)"
+           if cpu else "") for k, v in per.items()))
+    return out
 
 
 def bench_extensions(reps: int = 20):
@@ -450,10 +717,13 @@ def bench_sweep():
                        for r in res]}
 
 
-def bench_adjoint(reps: int = 3):
+def bench_adjoint(reps: int = 3, cpu: bool = True):
     """Differentiable rollout: 16,384 agents, 50 steps, checkpoints every 10:
     forward rollout, then the backward pass (segment replays and
-    orca_step_backward), timed with HIP events."""
+    orca_step_backward), timed with HIP events.  The per-agent adjoint
+    kernel is timed alone (events around it) over the backward steps of the
+    rollout's own trajectory; the oracle's gradient of the same rollout
+    (forward, then its one-step VJPs chained backwards) is timed beside it."""
     import numpy as np
     import torch
     from paper_2008_11578_amd import orca, rollout, scenarios
@@ -482,13 +752,75 @@ def bench_adjoint(reps: int = 3):
     runs = [once() for _ in range(reps)]
     fwd = float(np.median([r[0] for r in runs]))
     bwd = float(np.median([r[1] for r in runs]))
-    log(f"[bench] adjoint {n} agents x {steps} steps: forward {fwd:.2f} ms, backward {bwd:.2f} ms")
-    return {"metric": "agent-steps/s of a differentiable rollout (forward + backward)",
-            "agents": n, "steps": steps, "checkpoint_every": 10, "forward_ms": fwd,
-            "backward_ms": bwd,
-            "agent_steps_per_s": n * steps / ((fwd + bwd) * 1e-3),
-            "backward_agent_steps_per_s": n * steps / (bwd * 1e-3),
-            "loss": runs[-1][2], "dL_dtau": runs[-1][3]}
+    # the adjoint kernel alone over the rollout's trajectory
+    import dataclasses
+    pv = dataclasses.replace(p, pref_is_goal=0)
+    s, s2 = st0.clone(), st0.clone()
+    ws = orca.Workspace(n)
+    states = []
+    for _ in range(steps):
+        states.append(s.clone())
+        orca.step(s, pv, ws, out=s2)
+        s, s2 = s2, s
+    wsb = orca.Workspace(n, backward=True)
+    gen = torch.Generator(device="cuda").manual_seed(9)
+    g = [torch.randn(n, device="cuda", generator=gen) for _ in range(4)]
+    gpr = [torch.zeros(n, device="cuda") for _ in range(2)]
+    gt = torch.zeros(1, device="cuda")
+    out4 = tuple(torch.empty(n, device="cuda") for _ in range(4))
+    hip = HipEvents()
+    pre = [(hip.create(), hip.create(), hip.create()) for _ in range(steps)]
+    for t in range(steps - 1, -1, -1):
+        orca.step_backward(states[t], pv, wsb, *g, gpr[0], gpr[1], gt, out=out4, events=pre[t])
+    torch.cuda.synchronize()
+    k_ms = float(np.mean([hip.elapsed_ms(e[1], e[2]) for e in pre]))
+    hip.close()
+    log(f"[bench] adjoint {n} agents x {steps} steps: forward {fwd:.2f} ms, backward {bwd:.2f} ms, "
+        f"adjoint kernel {k_ms * 1e3:.1f} us")
+    out = {"metric": "agent-steps/s of a differentiable rollout (forward + backward)",
+           "agents": n, "steps": steps, "checkpoint_every": 10, "forward_ms": fwd,
+           "backward_ms": bwd, "adjoint_kernel_ms": k_ms,
+           "agent_steps_per_s": n * steps / ((fwd + bwd) * 1e-3),
+           "backward_agent_steps_per_s": n * steps / (bwd * 1e-3),
+           "loss": runs[-1][2], "dL_dtau": runs[-1][3]}
+    if cpu:
+        import oracle
+        oracle.build(force=False)
+        snaps = [states[0].to_numpy(), states[-1].to_numpy()]
+        ops = []
+        for snap in snaps:
+            w = oracle.step(snap, pv, want_work=True)["work"]
+            ops.append(algorithmic_ops(w) + ADJ_OPS_PER_NEIGHBOR * float(w[:, 2].sum())
+                       + ADJ_OPS_PER_AGENT * n)
+        out["roofline"] = alu_roofline(float(np.mean(ops)), k_ms, n, ADJ_BYTES_PER_AGENT,
+                                       f"k_adjoint<{p.max_neighbors}>")
+        st = {k: np.array(getattr(sc, k), dtype=np.uint8 if k == "cls" else np.float64)
+              for k in ("px", "py", "vx", "vy", "pref_x", "pref_y", "radius", "max_speed", "cls")}
+        full = oracle_threads()
+        oracle.set_threads(full)
+        t0 = time.perf_counter()
+        oracle.rollout_grad(st, p, steps, sc.target_x, sc.target_y)
+        el = time.perf_counter() - t0
+        steps1 = 5
+        oracle.set_threads(1)
+        try:
+            t1 = time.perf_counter()
+            oracle.rollout_grad(st, p, steps1, sc.target_x, sc.target_y)
+            el1 = time.perf_counter() - t1
+        finally:
+            oracle.set_threads(full)
+        rate = n * steps / el
+        out["cpu_baseline"] = {
+            "value": rate, "unit": "agent-steps/s (forward + backward)", "cores": full,
+            "kind": "oracle",
+            "sample": f"the oracle's gradient of the whole {steps}-step rollout (FP64 forward, "
+                      f"then its one-step VJPs chained backwards, {el:.2f} s); single thread: "
+                      f"a {steps1}-step rollout's gradient ({el1:.2f} s)",
+            "single_thread_value": n * steps1 / el1, "nproc": os.cpu_count(),
+            "cpu_model": cpu_model(), "speedup": out["agent_steps_per_s"] / rate}
+        log(f"[bench] adjoint oracle {rate:.3e} agent-steps/s on {full} threads; adjoint kernel "
+            f"roofline frac {out['roofline']['frac']:.3f}")
+    return out
 
 
 def main(argv=None):
@@ -516,6 +848,8 @@ def main(argv=None):
                     help="skip the lifecycle / overlap / acceleration-cap leg")
     ap.add_argument("--no-vehicle-share", dest="vehicle_share", action="store_false",
                     help="skip the vehicle-share sweep of the mixed crowd")
+    ap.add_argument("--no-legs", dest="legs", action="store_false",
+                    help="skip the 256-agent and mixed-crowd configuration runs")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) and exit: the "
                          "reference kernel for scaling HBM counters")
@@ -549,38 +883,23 @@ def main(argv=None):
     n = sc.n
     params = dataclasses.replace(sc.params, cell_size=args.cell_size)
     log(f"[bench] workload {sc.name}: n={n}, k={params.max_neighbors}, R_n={params.neighbor_dist}")
-    state = orca.State.from_arrays(sc)
-    nxt = state.clone()
-    ws = orca.Workspace(n)
-    status = torch.zeros(n, dtype=torch.uint8, device="cuda")
-
-    for _ in range(args.warmup):
-        orca.step(state, params, ws, out=nxt, status=status)
-        state, nxt = nxt, state
-    torch.cuda.synchronize()
-    snap_start = state.to_numpy()
-    hip = HipEvents()
-    # pre-create the events so that creation stays outside the timed region
-    pre = [(hip.create(), hip.create(), hip.create()) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        orca.step(state, params, ws, out=nxt, status=status, events=pre[s])
-        state, nxt = nxt, state
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    grid_ms = [hip.elapsed_ms(a, b) for a, b, c in pre]
-    step_ms = [hip.elapsed_ms(b, c) for a, b, c in pre]
-    hip.close()
-    lp3_share = float(status.float().mean().item())
-    snap_end = state.to_numpy()
-
+    r = run_plain(sc, params, args.steps, args.warmup)
+    snap_start, snap_end = r["start"], r["end"]
+    wall, g_ms, k_ms, lp3_share = r["wall"], r["grid_ms"], r["k_ms"], r["lp3_share"]
     ms_per_step = wall * 1e3 / args.steps
     value = n * args.steps / wall
-    k_ms = float(np.mean(step_ms))
-    g_ms = float(np.mean(grid_ms))
     log(f"[bench] {args.steps} steps: {ms_per_step:.3f} ms/step, grid {g_ms:.3f} ms, "
         f"step kernel {k_ms:.3f} ms, LP3 share at end {lp3_share:.3f}")
+
+    # the grid geometry of the state closing the timed window (cells used)
+    st_end = orca.State.from_arrays(snap_end)
+    wsg = orca.Workspace(n)
+    orca.build_grid(st_end, params, wsg, want_neighbors=False)
+    torch.cuda.synchronize()
+    meta = wsg.buf[:64].cpu().numpy()
+    n_cells = int(meta[28:32].view(np.int32)[0])  # GridMeta.n_cells
+    grid = grid_kernels_from_profile(n, n_cells, g_ms)
+    del wsg, st_end
 
     cpu = None
     ops_per_launch = None
@@ -593,22 +912,22 @@ def main(argv=None):
                          f"GPU window plus 1 from the state closing it, {n} agents "
                          f"({el:.1f} s); single-thread rate from 2 steps of the same state",
                "single_thread_value": rate_1t, "nproc": os.cpu_count(),
-               "cpu_model": cpu_model()}
+               "cpu_model": cpu_model(), "speedup": value / rate}
         log(f"[bench] oracle: {rate:.3e} agent-steps/s on {threads} threads ({el:.1f} s), "
             f"{rate_1t:.3e} on 1 thread")
 
     roof = None
     if ops_per_launch is not None:
-        achieved = ops_per_launch / (k_ms * 1e-3) / 1e12
         kh = source_hash()
+        roof = alu_roofline(ops_per_launch, k_ms, n, STEP_BYTES_PER_AGENT,
+                            f"k_step<{params.max_neighbors}>", source_hash=kh)
         traffic = traffic_from_profile(kh)
-        roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Top/s",
-                "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
-                "kernel": f"k_step<{params.max_neighbors}>", "kernel_ms": k_ms,
-                "ops_per_launch": ops_per_launch,
-                "hbm_algorithmic_GBs": STEP_BYTES_PER_AGENT * n / (k_ms * 1e-3) / 1e9,
-                "hbm_measured_GBs": (traffic / (k_ms * 1e-3) / 1e9) if traffic else None,
-                "hbm_peak_GBs": HBM_PEAK_GBS, "source_hash": kh}
+        if traffic:
+            roof.update(traffic=traffic["bytes"], traffic_raw_fetch_kib=traffic["fetch_kib"],
+                        traffic_raw_write_kib=traffic["write_kib"],
+                        traffic_scale=traffic["scale"],
+                        hbm_measured_GBs=traffic["bytes"] / (k_ms * 1e-3) / 1e9,
+                        hbm_measured_frac=traffic["bytes"] / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
         valu = valu_from_profile(kh)
         if valu:
             # lane-ops the hardware executed (active lanes of every VALU
@@ -618,9 +937,18 @@ def main(argv=None):
             roof.update(valu, executed_lane_ops_Tps=executed,
                         executed_frac=executed / VALU_PEAK_TOPS)
 
-    batched = bench_batched(args.batched_steps) if args.batched_steps > 0 else None
-    adjoint = bench_adjoint() if args.adjoint else None
-    vshare = bench_vehicle_share() if args.vehicle_share else None
+    legs = None
+    if args.legs:
+        c1 = scenarios.c1_plain()
+        c2 = scenarios.c2_mixed()
+        legs = {"c1": bench_config_leg("c1", c1, c1.params, c1.steps, c1.steps,
+                                       cpu=args.cpu_steps > 0),
+                "c2": bench_config_leg("c2", c2, c2.params, c2.steps, 10,
+                                       cpu=args.cpu_steps > 0)}
+    cpu_on = args.cpu_steps > 0
+    batched = bench_batched(args.batched_steps, cpu=cpu_on) if args.batched_steps > 0 else None
+    adjoint = bench_adjoint(cpu=cpu_on) if args.adjoint else None
+    vshare = bench_vehicle_share(cpu=cpu_on) if args.vehicle_share else None
     ext = bench_extensions() if args.extensions else None
     cross = bench_crossing() if args.crossing else None
     sweep = bench_sweep() if args.sweep else None
@@ -645,6 +973,8 @@ def main(argv=None):
                    "grid_ms": g_ms, "step_kernel_ms": k_ms, "lp3_share_end": lp3_share},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "grid_kernels": grid,
+        "legs": legs,
         "batched": batched,
         "adjoint": adjoint,
         "vehicle_share": vshare,

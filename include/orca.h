@@ -144,6 +144,19 @@ int orca_step_ex(const orca_agents_in *in, const orca_agents_out *out, int32_t n
                  const orca_params *params, void *ws, size_t ws_bytes,
                  const orca_step_events *events, hipStream_t stream);
 
+/* orca_step that also writes the neighbour lists this step used, in the
+ * format of orca_build_grid: nbr (n x max_neighbors, row-major, nullable)
+ * the caller indices of each agent's nearest neighbours, ascending in
+ * (squared distance, index), padded with -1; nbr_count (n, nullable) their
+ * number.  The step itself (outputs, and what the workspace keeps for the
+ * next step) is the same as orca_step's, bit for bit; the lists are those
+ * of the selection narrowed by the distances the workspace kept from the
+ * previous step, which must equal orca_build_grid's exact lists.  For
+ * checking and inspection (Sec. 3: each agent observes its nearby agents). */
+int orca_step_nbr(const orca_agents_in *in, const orca_agents_out *out, int32_t n,
+                  const orca_params *params, void *ws, size_t ws_bytes, int32_t *nbr,
+                  int32_t *nbr_count, hipStream_t stream);
+
 /* Description of a batch of independent scenes for orca_step_batched.
  * Scene s owns the agents [scene_off[s], scene_off[s+1]) of the agent arrays
  * and uses params[s]; agents of different scenes never interact.  This
@@ -183,6 +196,12 @@ typedef struct {
 int orca_step_batched(const orca_agents_in *in, const orca_agents_out *out, int32_t n,
                       const orca_batch *batch, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* orca_step_batched with phase events (any may be NULL): before the batch's
+ * grid build, before its step kernel, after it.  Timing only. */
+int orca_step_batched_ex(const orca_agents_in *in, const orca_agents_out *out, int32_t n,
+                         const orca_batch *batch, void *ws, size_t ws_bytes,
+                         const orca_step_events *events, hipStream_t stream);
+
 /* Cotangents (gradients of a scalar loss) of an agent state, device
  * pointers, length n, caller order. */
 typedef struct {
@@ -216,6 +235,13 @@ size_t orca_backward_workspace_bytes(int32_t n, int32_t max_cells);
 int orca_step_backward(const orca_agents_in *in, int32_t n, const orca_params *params,
                        const orca_cotangents *g1, const orca_cotangents_out *g0, void *ws,
                        size_t ws_bytes, hipStream_t stream);
+
+/* orca_step_backward with phase events (any may be NULL): before the grid
+ * build, before the per-agent adjoint kernel (recomputation and VJP), after
+ * it (the transpose gather and the tau sum follow).  Timing only. */
+int orca_step_backward_ex(const orca_agents_in *in, int32_t n, const orca_params *params,
+                          const orca_cotangents *g1, const orca_cotangents_out *g0, void *ws,
+                          size_t ws_bytes, const orca_step_events *events, hipStream_t stream);
 
 /* ---- Agent lifecycle (Sec. 4, first experiment) -------------------------
  * In the crossing experiments agents are spawned in start regions at points

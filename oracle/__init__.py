@@ -32,7 +32,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB) or \
             any(os.path.getmtime(_LIB) < os.path.getmtime(s) for s in srcs):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fPIC",
+        subprocess.check_call(["g++", "-O3", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-fPIC",
                                "-shared", "-Wall", "-o", tmp, *srcs, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB

@@ -619,7 +619,8 @@ hipError_t launch_adjoint(const orca_agents_in &in, int n, const orca_params &pr
                           const Layout &L, const Work &w, const AdjointBufs &b,
                           const float *gpx1, const float *gpy1, const float *gvx1,
                           const float *gvy1, float *gpx0, float *gpy0, float *gvx0, float *gvy0,
-                          float *gprx, float *gpry, float *g_tau, hipStream_t stream)
+                          float *gprx, float *gpry, float *g_tau, const orca_step_events *ev,
+                          hipStream_t stream)
 {
     (void)L;
     AdjArgs a;
@@ -645,6 +646,8 @@ hipError_t launch_adjoint(const orca_agents_in &in, int n, const orca_params &pr
     a.e_val = b.e_val;
     a.e_cnt = b.e_cnt;
     const int k = prm.max_neighbors;
+    if (ev && ev->step_begin && hipEventRecord(ev->step_begin, stream) != hipSuccess)
+        return hipErrorInvalidValue;
     if (k <= 4)
         launch_adjoint_k<4>(a, stream);
     else if (k <= 8)
@@ -661,6 +664,8 @@ hipError_t launch_adjoint(const orca_agents_in &in, int n, const orca_params &pr
         launch_adjoint_k<24>(a, stream);
     else
         launch_adjoint_k<32>(a, stream);
+    if (ev && ev->step_end && hipEventRecord(ev->step_end, stream) != hipSuccess)
+        return hipErrorInvalidValue;
     const int ne = kEdges * n;
     const int nbe = (ne + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_edge_count, dim3(nbe), dim3(kBlock), 0, stream, b.e_tgt, ne, n, b.e_cnt,

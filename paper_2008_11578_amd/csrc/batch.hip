@@ -255,10 +255,13 @@ hipError_t launch_step_batched_k(const BatchArgs &a, int mode, bool acc, int blo
 hipError_t launch_batched(const orca_agents_in &in, const orca_agents_out &out, int n,
                           const int32_t *scene_off, int n_scenes, const orca_params *params,
                           int k_max, bool acc, int block, const Layout &L, const Work &w,
-                          int32_t *error_flag, int mode, hipStream_t stream)
+                          int32_t *error_flag, int mode, const orca_step_events *ev,
+                          hipStream_t stream)
 {
     const int S = n_scenes;
     const int nb = (n + kBlock - 1) / kBlock;
+    if (ev && ev->grid_begin && hipEventRecord(ev->grid_begin, stream) != hipSuccess)
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_batch_bbox, dim3(S), dim3(kBlock), 0, stream, in.px, in.py, n, scene_off,
                        S, params, w.partial, w.count, (int)L.max_cells, w.queue, error_flag,
                        acc ? 1 : 0);
@@ -281,14 +284,28 @@ hipError_t launch_batched(const orca_agents_in &in, const orca_agents_out &out, 
     a.s1 = w.s1;
     a.queue = w.queue;
     a.guess = w.guess;
-    if (k_max <= 4) return launch_step_batched_k<4>(a, mode, acc, block, stream);
-    if (k_max <= 8) return launch_step_batched_k<8>(a, mode, acc, block, stream);
-    if (k_max <= 10) return launch_step_batched_k<10>(a, mode, acc, block, stream);
-    if (k_max <= 12) return launch_step_batched_k<12>(a, mode, acc, block, stream);
-    if (k_max <= 16) return launch_step_batched_k<16>(a, mode, acc, block, stream);
-    if (k_max <= 20) return launch_step_batched_k<20>(a, mode, acc, block, stream);
-    if (k_max <= 24) return launch_step_batched_k<24>(a, mode, acc, block, stream);
-    return launch_step_batched_k<32>(a, mode, acc, block, stream);
+    if (ev && ev->step_begin && hipEventRecord(ev->step_begin, stream) != hipSuccess)
+        return hipErrorInvalidValue;
+    if (k_max <= 4)
+        e = launch_step_batched_k<4>(a, mode, acc, block, stream);
+    else if (k_max <= 8)
+        e = launch_step_batched_k<8>(a, mode, acc, block, stream);
+    else if (k_max <= 10)
+        e = launch_step_batched_k<10>(a, mode, acc, block, stream);
+    else if (k_max <= 12)
+        e = launch_step_batched_k<12>(a, mode, acc, block, stream);
+    else if (k_max <= 16)
+        e = launch_step_batched_k<16>(a, mode, acc, block, stream);
+    else if (k_max <= 20)
+        e = launch_step_batched_k<20>(a, mode, acc, block, stream);
+    else if (k_max <= 24)
+        e = launch_step_batched_k<24>(a, mode, acc, block, stream);
+    else
+        e = launch_step_batched_k<32>(a, mode, acc, block, stream);
+    if (e != hipSuccess) return e;
+    if (ev && ev->step_end && hipEventRecord(ev->step_end, stream) != hipSuccess)
+        return hipErrorInvalidValue;
+    return hipSuccess;
 }
 
 }  // namespace orca

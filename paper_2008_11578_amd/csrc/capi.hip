@@ -225,9 +225,14 @@ int orca_build_grid(const orca_agents_in *in, int32_t n, const orca_params *para
     return ORCA_OK;
 }
 
-int orca_step_ex(const orca_agents_in *in, const orca_agents_out *out, int32_t n,
-                 const orca_params *params, void *ws, size_t ws_bytes,
-                 const orca_step_events *events, hipStream_t stream)
+}  // extern "C"
+
+namespace {
+
+int step_impl(const orca_agents_in *in, const orca_agents_out *out, int32_t n,
+              const orca_params *params, void *ws, size_t ws_bytes,
+              const orca_step_events *events, int32_t *nbr, int32_t *nbr_count,
+              hipStream_t stream)
 {
     Layout L{};
     int rc = prepare(n, params, ws, ws_bytes, L);
@@ -242,20 +247,46 @@ int orca_step_ex(const orca_agents_in *in, const orca_agents_out *out, int32_t n
     if (launch_grid_build(*in, n, *params, L, w, stream) != hipSuccess) return ORCA_EHIP;
     if (events && events->step_begin && hipEventRecord(events->step_begin, stream) != hipSuccess)
         return ORCA_EHIP;
-    if (launch_step(*in, *out, n, *params, L, w, stream) != hipSuccess) return ORCA_EHIP;
+    if (launch_step(*in, *out, n, *params, L, w, nbr, nbr_count, stream) != hipSuccess)
+        return ORCA_EHIP;
     if (events && events->step_end && hipEventRecord(events->step_end, stream) != hipSuccess)
         return ORCA_EHIP;
     return ORCA_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int orca_step_ex(const orca_agents_in *in, const orca_agents_out *out, int32_t n,
+                 const orca_params *params, void *ws, size_t ws_bytes,
+                 const orca_step_events *events, hipStream_t stream)
+{
+    return step_impl(in, out, n, params, ws, ws_bytes, events, nullptr, nullptr, stream);
+}
+
 int orca_step(const orca_agents_in *in, const orca_agents_out *out, int32_t n,
               const orca_params *params, void *ws, size_t ws_bytes, hipStream_t stream)
 {
-    return orca_step_ex(in, out, n, params, ws, ws_bytes, nullptr, stream);
+    return step_impl(in, out, n, params, ws, ws_bytes, nullptr, nullptr, nullptr, stream);
+}
+
+int orca_step_nbr(const orca_agents_in *in, const orca_agents_out *out, int32_t n,
+                  const orca_params *params, void *ws, size_t ws_bytes, int32_t *nbr,
+                  int32_t *nbr_count, hipStream_t stream)
+{
+    return step_impl(in, out, n, params, ws, ws_bytes, nullptr, nbr, nbr_count, stream);
 }
 
 int orca_step_batched(const orca_agents_in *in, const orca_agents_out *out, int32_t n,
                       const orca_batch *batch, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    return orca_step_batched_ex(in, out, n, batch, ws, ws_bytes, nullptr, stream);
+}
+
+int orca_step_batched_ex(const orca_agents_in *in, const orca_agents_out *out, int32_t n,
+                         const orca_batch *batch, void *ws, size_t ws_bytes,
+                         const orca_step_events *events, hipStream_t stream)
 {
     if (n < 0 || n > ORCA_N_MAX || !batch) return ORCA_EINVAL;
     if (batch->n_scenes < 1 || !batch->scene_off || !batch->params) return ORCA_EINVAL;
@@ -279,7 +310,7 @@ int orca_step_batched(const orca_agents_in *in, const orca_agents_out *out, int3
     if (launch_batched(*in, *out, n, batch->scene_off, batch->n_scenes, batch->params,
                        batch->k_tile ? batch->k_tile : batch->max_neighbors,
                        batch->has_accel != 0, batch->block ? batch->block : 128, L, w,
-                       batch->error_flag, batch->mode, stream) != hipSuccess)
+                       batch->error_flag, batch->mode, events, stream) != hipSuccess)
         return ORCA_EHIP;
     return ORCA_OK;
 }
@@ -293,6 +324,13 @@ size_t orca_backward_workspace_bytes(int32_t n, int32_t max_cells)
 int orca_step_backward(const orca_agents_in *in, int32_t n, const orca_params *params,
                        const orca_cotangents *g1, const orca_cotangents_out *g0, void *ws,
                        size_t ws_bytes, hipStream_t stream)
+{
+    return orca_step_backward_ex(in, n, params, g1, g0, ws, ws_bytes, nullptr, stream);
+}
+
+int orca_step_backward_ex(const orca_agents_in *in, int32_t n, const orca_params *params,
+                          const orca_cotangents *g1, const orca_cotangents_out *g0, void *ws,
+                          size_t ws_bytes, const orca_step_events *events, hipStream_t stream)
 {
     if (n < 0 || n > ORCA_N_MAX) return ORCA_EINVAL;
     int rc = check_params(params);
@@ -313,9 +351,12 @@ int orca_step_backward(const orca_agents_in *in, int32_t n, const orca_params *p
     if (L.total + extra > ws_bytes) return ORCA_EWORKSPACE;
     const Work w = bind(L, ws);
     const AdjointBufs b = bind_adjoint(n, (char *)ws + L.total);
+    if (events && events->grid_begin && hipEventRecord(events->grid_begin, stream) != hipSuccess)
+        return ORCA_EHIP;
     if (launch_grid_build(*in, n, *params, L, w, stream) != hipSuccess) return ORCA_EHIP;
     if (launch_adjoint(*in, n, *params, L, w, b, g1->px, g1->py, g1->vx, g1->vy, g0->px, g0->py,
-                       g0->vx, g0->vy, g0->pref_x, g0->pref_y, g0->tau, stream) != hipSuccess)
+                       g0->vx, g0->vy, g0->pref_x, g0->pref_y, g0->tau, events,
+                       stream) != hipSuccess)
         return ORCA_EHIP;
     return ORCA_OK;
 }

@@ -207,6 +207,9 @@ __device__ __forceinline__ bool row_range(const GridMeta &g, const uint32_t *__r
 
 // Sorting network over N (a power of two) 64-bit keys held in registers,
 // ascending; every index is a compile-time constant.
+// Largest fixed-point sort key: 26 bits above the 6-bit buffer slot.
+constexpr uint32_t kSortKeyMax = (1u << 26) - 1u;
+
 template <int K>
 struct SortNet {
     static constexpr int N = K <= 8 ? 16 : (K <= 24 ? 32 : 64);
@@ -394,7 +397,10 @@ __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
                 if (p < (int)take) {
                     const float fk = __uint_as_float(
                         (uint32_t)(buf[buf_idx<BLOCK>(p, tid)] >> 32));
-                    const uint32_t q = (uint32_t)fminf(fk * qscale, 67108863.0f);
+                    // clamp in the integer domain: the FP32 product reaches
+                    // 2^26 for keys within a few 1e-8 (relative) below r2c,
+                    // and 2^26 - 1 has no FP32 value to clamp to
+                    const uint32_t q = min((uint32_t)(fk * qscale), kSortKeyMax);
                     w = (q << 6) | (uint32_t)p;
                 }
                 e[p] = w;
@@ -893,14 +899,17 @@ __device__ __forceinline__ void desired_velocity(const SceneP &p, float xi, floa
 // column tid.  `guess` (caller order, nullable) keeps each agent's K-th
 // neighbour distance between steps (0: none); it only narrows the counting
 // pass.  ACC compiles the acceleration lines in (used for agents whose class
-// has a cap).
-template <int K, int BLOCK, bool ACC = false>
+// has a cap).  EXPORT also writes the neighbour list the step used (caller
+// indices, ascending, -1 padded) to nbr[i * kout ..] and its length to
+// cnt[i] (either nullable); the step itself is unchanged.
+template <int K, int BLOCK, bool ACC = false, bool EXPORT = false>
 __device__ __forceinline__ void step_agent(int s, const GridMeta &g, const SceneP &p,
                                            const orca_agents_in &in, const orca_agents_out &out,
                                            const uint32_t *__restrict__ start,
                                            const float4 *__restrict__ s0,
                                            const float4 *__restrict__ s1, float4 *lines, int tid,
-                                           float *__restrict__ guess)
+                                           float *__restrict__ guess, int32_t *nbr = nullptr,
+                                           int32_t *cnt = nullptr, int kout = 0)
 {
     const float4 me0 = s0[s];
     const float4 me1 = s1[s];
@@ -931,6 +940,14 @@ __device__ __forceinline__ void step_agent(int s, const GridMeta &g, const Scene
     uint32_t pos[K];
 #pragma unroll
     for (int q = 0; q < K; ++q) pos[q] = q < m ? entry_pos(buf[buf_idx<BLOCK>(q, tid)]) : 0u;
+    if (EXPORT) {
+        if (nbr) {
+            int32_t *row = nbr + (int64_t)i * kout;
+            for (int q = 0; q < kout; ++q)
+                row[q] = q < m ? __float_as_int(s0[entry_pos(buf[buf_idx<BLOCK>(q, tid)])].z) : -1;
+        }
+        if (cnt) cnt[i] = m;
+    }
 
     float prx = in.pref_x[i], pry = in.pref_y[i];
     const float acc = ACC ? (ci ? p.acc1 : p.acc0) : 0.0f;

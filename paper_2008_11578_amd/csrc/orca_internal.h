@@ -223,11 +223,14 @@ hipError_t launch_scan_scatter(const orca_agents_in &in, int n, const Layout &L,
 hipError_t launch_batched(const orca_agents_in &in, const orca_agents_out &out, int n,
                           const int32_t *scene_off, int n_scenes, const orca_params *params,
                           int k_max, bool acc, int block, const Layout &L, const Work &w,
-                          int32_t *error_flag, int mode, hipStream_t stream);
+                          int32_t *error_flag, int mode, const orca_step_events *ev,
+                          hipStream_t stream);
 
-// Fused neighbour search + half-planes + LP + update for one scene.
+// Fused neighbour search + half-planes + LP + update for one scene; with
+// nbr / cnt (nullable) also the neighbour lists the step used.
 hipError_t launch_step(const orca_agents_in &in, const orca_agents_out &out, int n,
-                       const orca_params &p, const Layout &L, const Work &w, hipStream_t stream);
+                       const orca_params &p, const Layout &L, const Work &w, int32_t *nbr,
+                       int32_t *cnt, hipStream_t stream);
 
 // Neighbour lists only (caller order), for orca_build_grid.
 hipError_t launch_knn_export(const orca_agents_in &in, int n, const orca_params &p,
@@ -271,6 +274,7 @@ hipError_t launch_adjoint(const orca_agents_in &in, int n, const orca_params &pr
                           const Layout &L, const Work &w, const AdjointBufs &b,
                           const float *gpx1, const float *gpy1, const float *gvx1,
                           const float *gvy1, float *gpx0, float *gpy0, float *gvx0, float *gvy0,
-                          float *gprx, float *gpry, float *g_tau, hipStream_t stream);
+                          float *gprx, float *gpry, float *g_tau, const orca_step_events *ev,
+                          hipStream_t stream);
 
 }  // namespace orca

@@ -1,7 +1,8 @@
 // Fused ORCA step for one scene on gfx950: one lane per agent, agents taken in
 // cell order so that the lanes of a wavefront share neighbour candidates; the
 // per-agent work (exact kNN, half-planes, LP2, LP3, update) is
-// dev::step_agent.  Also the neighbour-list export of orca_build_grid.
+// dev::step_agent.  Also the neighbour-list export of orca_build_grid and of
+// orca_step_nbr.
 #include "orca_device.h"
 
 namespace orca {
@@ -28,7 +29,8 @@ using dev::buf_idx;
 using dev::KnnShape;
 using dev::knn_select;
 
-template <int K, int BLOCK, bool ACC>
+// EXPORT: the same step, also writing the neighbour lists it used.
+template <int K, int BLOCK, bool ACC, bool EXPORT>
 __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, dev::SceneP p)
 {
     __shared__ float4 lines[dev::KnnShape<K>::kSlots * BLOCK];
@@ -36,8 +38,8 @@ __global__ __launch_bounds__(BLOCK) void k_step(StepArgs a, dev::SceneP p)
     const int s = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + tid;
     if (s >= a.n) return;
     const GridMeta g = *a.meta;
-    dev::step_agent<K, BLOCK, ACC>(s, g, p, a.in, a.out, a.start, a.s0, a.s1, lines, tid,
-                                   a.guess);
+    dev::step_agent<K, BLOCK, ACC, EXPORT>(s, g, p, a.in, a.out, a.start, a.s0, a.s1, lines, tid,
+                                           a.guess, a.nbr, a.cnt, a.k);
 }
 
 template <int K, int BLOCK>
@@ -88,13 +90,23 @@ template <int K>
 void launch_step_k(const StepArgs &a, hipStream_t stream)
 {
     const int nb = (a.n + kStepBlock - 1) / kStepBlock;
-    // the variant with acceleration lines only when a class has a cap
-    if (a.prm.accel[0] > 0.0f || a.prm.accel[1] > 0.0f)
-        hipLaunchKernelGGL((k_step<K, kStepBlock, true>), dim3(nb), dim3(kStepBlock), 0, stream,
-                           a, dev::scene_params(a.prm));
+    // the variant with acceleration lines only when a class has a cap, the
+    // exporting variant only when lists are asked for
+    const bool acc = a.prm.accel[0] > 0.0f || a.prm.accel[1] > 0.0f;
+    const bool exp = a.nbr || a.cnt;
+    const dev::SceneP p = dev::scene_params(a.prm);
+    if (acc && exp)
+        hipLaunchKernelGGL((k_step<K, kStepBlock, true, true>), dim3(nb), dim3(kStepBlock), 0,
+                           stream, a, p);
+    else if (acc)
+        hipLaunchKernelGGL((k_step<K, kStepBlock, true, false>), dim3(nb), dim3(kStepBlock), 0,
+                           stream, a, p);
+    else if (exp)
+        hipLaunchKernelGGL((k_step<K, kStepBlock, false, true>), dim3(nb), dim3(kStepBlock), 0,
+                           stream, a, p);
     else
-        hipLaunchKernelGGL((k_step<K, kStepBlock, false>), dim3(nb), dim3(kStepBlock), 0, stream,
-                           a, dev::scene_params(a.prm));
+        hipLaunchKernelGGL((k_step<K, kStepBlock, false, false>), dim3(nb), dim3(kStepBlock), 0,
+                           stream, a, p);
 }
 
 template <int K>
@@ -129,10 +141,13 @@ void launch_knn_k(const StepArgs &a, hipStream_t stream)
     } while (0)
 
 hipError_t launch_step(const orca_agents_in &in, const orca_agents_out &out, int n,
-                       const orca_params &p, const Layout &L, const Work &w, hipStream_t stream)
+                       const orca_params &p, const Layout &L, const Work &w, int32_t *nbr,
+                       int32_t *cnt, hipStream_t stream)
 {
     (void)L;
-    const StepArgs a = make_args(in, &out, n, p, w);
+    StepArgs a = make_args(in, &out, n, p, w);
+    a.nbr = nbr;
+    a.cnt = cnt;
     ORCA_DISPATCH_K(launch_step_k, p.max_neighbors, a, stream);
     return hipGetLastError();
 }

@@ -99,9 +99,21 @@ def lib() -> ctypes.CDLL:
         L.orca_step_ex.argtypes = [ctypes.POINTER(AgentsIn), ctypes.POINTER(AgentsOut), i32,
                                    ctypes.POINTER(OrcaParams), vp, sz,
                                    ctypes.POINTER(StepEvents), vp]
+        L.orca_step_nbr.restype = ctypes.c_int
+        L.orca_step_nbr.argtypes = [ctypes.POINTER(AgentsIn), ctypes.POINTER(AgentsOut), i32,
+                                    ctypes.POINTER(OrcaParams), vp, sz, vp, vp, vp]
         L.orca_step_batched.restype = ctypes.c_int
         L.orca_step_batched.argtypes = [ctypes.POINTER(AgentsIn), ctypes.POINTER(AgentsOut), i32,
                                         ctypes.POINTER(OrcaBatch), vp, sz, vp]
+        L.orca_step_batched_ex.restype = ctypes.c_int
+        L.orca_step_batched_ex.argtypes = [ctypes.POINTER(AgentsIn), ctypes.POINTER(AgentsOut),
+                                           i32, ctypes.POINTER(OrcaBatch), vp, sz,
+                                           ctypes.POINTER(StepEvents), vp]
+        L.orca_step_backward_ex.restype = ctypes.c_int
+        L.orca_step_backward_ex.argtypes = [ctypes.POINTER(AgentsIn), i32,
+                                            ctypes.POINTER(OrcaParams), ctypes.POINTER(Cotangents),
+                                            ctypes.POINTER(CotangentsOut), vp, sz,
+                                            ctypes.POINTER(StepEvents), vp]
         L.orca_backward_workspace_bytes.restype = sz
         L.orca_backward_workspace_bytes.argtypes = [i32, i32]
         L.orca_step_backward.restype = ctypes.c_int
@@ -286,6 +298,29 @@ def step(state: State, params, ws: Workspace, out: Optional[State] = None,
     return out
 
 
+def step_nbr(state: State, params, ws: Workspace, out: Optional[State] = None,
+             status: Optional[torch.Tensor] = None, stream=None):
+    """``orca_step_nbr``: the same step as :func:`step`, also returning the
+    neighbour lists it used, (out, nbr[n, k] int32, count[n] int32)."""
+    p = make_params(params)
+    n = state.n
+    if out is None:
+        out = state.clone()
+    if status is not None:
+        _check(status, "status", torch.uint8, n)
+    for k in ("px", "py", "vx", "vy"):
+        _check(getattr(out, k), "out." + k, torch.float32, n)
+    nbr = torch.empty((n, p.max_neighbors), dtype=torch.int32, device=state.px.device)
+    cnt = torch.empty(n, dtype=torch.int32, device=state.px.device)
+    ain = state.agents_in()
+    aout = AgentsOut(_ptr(out.px), _ptr(out.py), _ptr(out.vx), _ptr(out.vy), _ptr(status))
+    rc = lib().orca_step_nbr(ctypes.byref(ain), ctypes.byref(aout), n, ctypes.byref(p),
+                             ws.ptr(), ws.nbytes, _ptr(nbr), _ptr(cnt), _stream_handle(stream))
+    if rc != ORCA_OK:
+        raise OrcaError("orca_step_nbr", rc)
+    return out, nbr, cnt
+
+
 def params_of(sc: "scenarios.Scenario"):
     return sc.params
 
@@ -319,8 +354,10 @@ class Batch:
 
 
 def step_batched(state: State, batch: Batch, ws: Workspace, out: Optional[State] = None,
-                 status: Optional[torch.Tensor] = None, stream=None) -> State:
-    """One ORCA step of every scene of the batch (``orca_step_batched``)."""
+                 status: Optional[torch.Tensor] = None, stream=None, events=None) -> State:
+    """One ORCA step of every scene of the batch (``orca_step_batched``).
+    ``events``: optional (grid_begin, step_begin, step_end) raw hipEvent_t
+    handles (``orca_step_batched_ex``; timing only)."""
     n = state.n
     if out is None:
         out = state.clone()
@@ -331,8 +368,14 @@ def step_batched(state: State, batch: Batch, ws: Workspace, out: Optional[State]
     ain = state.agents_in()
     aout = AgentsOut(_ptr(out.px), _ptr(out.py), _ptr(out.vx), _ptr(out.vy), _ptr(status))
     b = batch.c_struct()
-    rc = lib().orca_step_batched(ctypes.byref(ain), ctypes.byref(aout), n, ctypes.byref(b),
-                                 ws.ptr(), ws.nbytes, _stream_handle(stream))
+    if events is None:
+        rc = lib().orca_step_batched(ctypes.byref(ain), ctypes.byref(aout), n, ctypes.byref(b),
+                                     ws.ptr(), ws.nbytes, _stream_handle(stream))
+    else:
+        ev = StepEvents(*events)
+        rc = lib().orca_step_batched_ex(ctypes.byref(ain), ctypes.byref(aout), n,
+                                        ctypes.byref(b), ws.ptr(), ws.nbytes, ctypes.byref(ev),
+                                        _stream_handle(stream))
     if rc != ORCA_OK:
         raise OrcaError("orca_step_batched", rc)
     return out
@@ -340,11 +383,14 @@ def step_batched(state: State, batch: Batch, ws: Workspace, out: Optional[State]
 
 def step_backward(state: State, params, ws: Workspace, g_px, g_py, g_vx, g_vy,
                   g_pref_x: torch.Tensor, g_pref_y: torch.Tensor,
-                  g_tau: Optional[torch.Tensor] = None, out=None, stream=None):
+                  g_tau: Optional[torch.Tensor] = None, out=None, stream=None, events=None):
     """Adjoint of one step at `state` (``orca_step_backward``).  g_* are the
     cotangents of the step's outputs; returns (g_px0, g_py0, g_vx0, g_vy0),
     written into `out` (a 4-tuple of tensors, which may be the inputs) or new
-    tensors.  g_pref_x/g_pref_y and g_tau (one float) are accumulated."""
+    tensors.  g_pref_x/g_pref_y and g_tau (one float) are accumulated.
+    ``events``: optional (grid_begin, step_begin, step_end) raw hipEvent_t
+    handles around the grid build and the per-agent adjoint kernel
+    (``orca_step_backward_ex``; timing only)."""
     n = state.n
     gin = (g_px, g_py, g_vx, g_vy)
     for k, t in zip(("g_px", "g_py", "g_vx", "g_vy"), gin):
@@ -361,8 +407,15 @@ def step_backward(state: State, params, ws: Workspace, g_px, g_py, g_vx, g_vy,
     ain = state.agents_in()
     c1 = Cotangents(*[_ptr(t) for t in gin])
     c0 = CotangentsOut(*[_ptr(t) for t in out], _ptr(g_pref_x), _ptr(g_pref_y), _ptr(g_tau))
-    rc = lib().orca_step_backward(ctypes.byref(ain), n, ctypes.byref(p), ctypes.byref(c1),
-                                  ctypes.byref(c0), ws.ptr(), ws.nbytes, _stream_handle(stream))
+    if events is None:
+        rc = lib().orca_step_backward(ctypes.byref(ain), n, ctypes.byref(p), ctypes.byref(c1),
+                                      ctypes.byref(c0), ws.ptr(), ws.nbytes,
+                                      _stream_handle(stream))
+    else:
+        ev = StepEvents(*events)
+        rc = lib().orca_step_backward_ex(ctypes.byref(ain), n, ctypes.byref(p), ctypes.byref(c1),
+                                         ctypes.byref(c0), ws.ptr(), ws.nbytes, ctypes.byref(ev),
+                                         _stream_handle(stream))
     if rc != ORCA_OK:
         raise OrcaError("orca_step_backward", rc)
     return out

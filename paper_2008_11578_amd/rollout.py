@@ -21,6 +21,9 @@ from . import orca
 class Rollout(torch.autograd.Function):
     @staticmethod
     def forward(ctx, v_pref_x, v_pref_y, tau, state0: orca.State, params, steps: int, ckpt: int):
+        # the step's scalar parameters travel by value to the kernels, so tau
+        # is read on the host once per rollout (one synchronisation when it
+        # lives on the device)
         p = dataclasses.replace(params, time_horizon=float(tau.detach().reshape(()).item()),
                                 pref_is_goal=0)
         n = state0.n
@@ -58,6 +61,12 @@ class Rollout(torch.autograd.Function):
         ws = orca.Workspace(n)
         wsb = orca.Workspace(n, backward=True)
         n_seg = len(ctx.ckpts)
+        # each replayed segment must end exactly where the forward pass went
+        # (the next checkpoint, or the final state): the gradient then belongs
+        # to the forward trajectory.  Mismatches are counted on the device and
+        # checked once at the end.
+        mismatch = torch.zeros((), dtype=torch.int64, device=dev)
+        ends = [tuple(getattr(base, k) for k in ("px", "py", "vx", "vy"))]
         for seg in range(n_seg - 1, -1, -1):
             t0 = seg * ckpt
             t1 = min(t0 + ckpt, steps)
@@ -70,9 +79,15 @@ class Rollout(torch.autograd.Function):
                 states.append(st.clone())
                 orca.step(st, p, ws, out=nxt)
                 st, nxt = nxt, st
+            want = ends[0] if seg == n_seg - 1 else ctx.ckpts[seg + 1]
+            for k, v in zip(("px", "py", "vx", "vy"), want):
+                mismatch += (getattr(st, k) != v).sum()
             for t in range(t1 - 1, t0 - 1, -1):
                 orca.step_backward(states[t - t0], p, wsb, gpx, gpy, gvx, gvy, g_prx, g_pry,
                                    g_tau, out=(gpx, gpy, gvx, gvy))
+        if int(mismatch.item()) != 0:
+            raise RuntimeError("rollout backward: a replayed segment left the forward trajectory "
+                               f"({int(mismatch.item())} differing values)")
         return g_prx, g_pry, g_tau.reshape(()), None, None, None, None
 
 

@@ -21,7 +21,8 @@ def test_profiles_parse_and_gate_on_source_hash():
     t = bench.traffic_from_profile(h)
     v = bench.valu_from_profile(h)
     if t is not None:   # taken on the current kernel source
-        assert 5e7 < t < 2e8
+        assert 5e7 < t["bytes"] < 2e8
+        assert t["fetch_kib"] > 0 and t["write_kib"] > 0
     if v is not None:
         assert 0 < v["valu_busy_pct"] <= 100 and 0 < v["valu_utilization_pct"] <= 100
         assert v["valu_insts_per_launch"] > 1e6
@@ -43,3 +44,18 @@ def test_algorithmic_ops_is_weighted_work():
     w[2, 3] = 7    # LP2 lines checked
     expect = 10 * bench.OP_COST[0] + 4 * bench.OP_COST[2] + 7 * bench.OP_COST[3]
     assert bench.algorithmic_ops(w) == expect
+
+
+def test_roofline_object():
+    r = bench.alu_roofline(3.9e9, 0.5, 1 << 20, bench.STEP_BYTES_PER_AGENT, "k")
+    assert r["bound"] == "alu" and r["unit"] == "Top/s"
+    np.testing.assert_allclose(r["achieved"], 3.9e9 / 0.5e-3 / 1e12)
+    np.testing.assert_allclose(r["frac"], r["achieved"] / r["peak"])
+    np.testing.assert_allclose(r["hbm_frac"], 49 * (1 << 20) / 0.5e-3 / 1e9 / 8000.0)
+
+
+def test_grid_kernel_bytes():
+    g = bench.grid_kernels_from_profile(1000, 500, 0.01)
+    assert g["algorithmic_bytes"] == (8 * 1000 + 4 * 500) + (16 * 1000 + 8 * 500) + 4 * 500 \
+        + 8 * 500 + 65 * 1000
+    assert 0 < g["hbm_frac_whole_build"] < 1

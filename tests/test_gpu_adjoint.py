@@ -99,23 +99,50 @@ def test_step_backward_deterministic_and_inplace():
     assert np.array_equal(a[1], gpr.cpu().numpy())
 
 
-def test_rollout_gradient_matches_oracle_chain():
+def component_err(g, ref):
+    """Per-parameter error measure of the rollout gradient:
+    |g - g_ref| / max(|g_ref|, 1e-3 max|g_ref|)."""
+    g, ref = np.asarray(g, np.float64), np.asarray(ref, np.float64)
+    return np.abs(g - ref) / np.maximum(np.abs(ref), 1e-3 * np.max(np.abs(ref)))
+
+
+def touching(states, params, tol=1e-4):
+    """Agents that at some state of the trajectory are within `tol` m of
+    touching one of their neighbours (||P| - R| < tol): there the velocity
+    obstacle changes form (reading 5) and its derivative grows like
+    1 / sqrt(|P|^2 - R^2), so FP32 and FP64 Jacobians part."""
+    flag = None
+    for s in states:
+        px = s["px"].astype(np.float64)
+        py = s["py"].astype(np.float64)
+        r = s["radius"].astype(np.float64)
+        nb, cn = oracle.knn(s["px"], s["py"], params.neighbor_dist, params.max_neighbors)
+        j = np.where(nb >= 0, nb, 0)
+        d = np.hypot(px[j] - px[:, None], py[j] - py[:, None]) - (r[j] + r[:, None])
+        near = (np.abs(d) < tol) & (nb >= 0)
+        f = near.any(axis=1)
+        flag = f if flag is None else (flag | f)
+    return flag
+
+
+def _rollout_vs_chain(sc, steps, ckpt, label):
+    """GPU rollout gradient (autograd through the checkpointed rollout)
+    against the oracle's VJPs chained backwards along the GPU's own FP32
+    trajectory, per parameter (C-12's measure) for every desired-velocity
+    component and tau."""
     import torch
     from paper_2008_11578_amd import orca, rollout
-    n, steps = 4096, 20
-    sc = scenarios.c5_rollout(n=n, side=120.0)
     p = sc.params
+    n = sc.n
     st0 = orca.State.from_arrays(sc)
     vpx = st0.pref_x.clone().requires_grad_(True)
     vpy = st0.pref_y.clone().requires_grad_(True)
-    tau = torch.tensor(float(p.time_horizon), device="cuda", requires_grad=True)
+    tau = torch.tensor(float(np.float32(p.time_horizon)), device="cuda", requires_grad=True)
     tx = torch.as_tensor(sc.target_x).cuda()
     ty = torch.as_tensor(sc.target_y).cuda()
-    px, py = rollout.rollout(vpx, vpy, tau, st0, p, steps=steps, ckpt=6)
-    loss = rollout.trajectory_loss(px, py, tx, ty)
-    loss.backward()
+    px, py = rollout.rollout(vpx, vpy, tau, st0, p, steps=steps, ckpt=ckpt)
+    rollout.trajectory_loss(px, py, tx, ty).backward()
     torch.cuda.synchronize()
-    # the GPU's own trajectory, then the oracle's VJPs chained backwards along it
     ws = orca.Workspace(n)
     s, s2 = st0.clone(), st0.clone()
     states = []
@@ -138,53 +165,32 @@ def test_rollout_gradient_matches_oracle_chain():
         gprx += r["g_pref_x"]
         gpry += r["g_pref_y"]
         gtau += r["g_tau"]
-    assert rel(vpx.grad.cpu().numpy(), gprx) <= 1e-3
-    assert rel(vpy.grad.cpu().numpy(), gpry) <= 1e-3
-    assert abs(tau.grad.item() - gtau) <= 1e-3 * abs(gtau)
+    g = np.concatenate([vpx.grad.cpu().numpy(), vpy.grad.cpu().numpy()])
+    ref = np.concatenate([gprx, gpry])
+    e = component_err(g, ref)
+    e_tau = abs(tau.grad.item() - gtau) / abs(gtau)
+    touch = touching(states, p)
+    exempt = np.concatenate([touch, touch])
+    worst = np.argsort(e)[-5:][::-1]
+    print(f"{label}: {e.size} components, err max {e.max():.2e} median {np.median(e):.2e}, "
+          f"over 1e-3: {int(np.sum(e > 1e-3))} ({int(np.sum((e > 1e-3) & exempt))} touching; "
+          f"{int(touch.sum())} agents touch); tau {tau.grad.item():.6g} vs {gtau:.6g} "
+          f"(err {e_tau:.1e}); worst {[(int(i % n), float(e[i]), bool(exempt[i])) for i in worst]}",
+          flush=True)
+    assert rel(g, ref) <= 1e-3
+    assert e_tau <= 1e-3
+    return e, exempt
+
+
+def test_rollout_gradient_matches_oracle_chain():
+    sc = scenarios.c5_rollout(n=4096, side=120.0)
+    e, exempt = _rollout_vs_chain(sc, 20, 6, "rollout 4096 x 20")
+    assert (e[~exempt] <= 1e-3).all()
 
 
 def test_rollout_gradient_full_shape_matches_oracle_chain():
     """16,384 agents, 50 steps, checkpoints every 10: the GPU gradient with
-    respect to all 32,768 desired-velocity components and tau against the
-    oracle's VJPs chained along the same (GPU) trajectory."""
-    import torch
-    from paper_2008_11578_amd import orca, rollout
+    respect to each of the 32,768 desired-velocity components and tau."""
     sc = scenarios.c5_rollout()
-    p = sc.params
-    n, steps = sc.n, sc.steps
-    st0 = orca.State.from_arrays(sc)
-    vpx = st0.pref_x.clone().requires_grad_(True)
-    vpy = st0.pref_y.clone().requires_grad_(True)
-    tau = torch.tensor(float(np.float32(p.time_horizon)), device="cuda", requires_grad=True)
-    tx = torch.as_tensor(sc.target_x).cuda()
-    ty = torch.as_tensor(sc.target_y).cuda()
-    px, py = rollout.rollout(vpx, vpy, tau, st0, p, steps=steps, ckpt=10)
-    rollout.trajectory_loss(px, py, tx, ty).backward()
-    torch.cuda.synchronize()
-    ws = orca.Workspace(n)
-    s, s2 = st0.clone(), st0.clone()
-    states = []
-    for _ in range(steps):
-        states.append(s.to_numpy())
-        orca.step(s, p, ws, out=s2)
-        s, s2 = s2, s
-    fin = s.to_numpy()
-    gpx = 2 * (fin["px"].astype(np.float64) - sc.target_x) / n
-    gpy = 2 * (fin["py"].astype(np.float64) - sc.target_y) / n
-    gvx = np.zeros(n)
-    gvy = np.zeros(n)
-    gprx = np.zeros(n)
-    gpry = np.zeros(n)
-    gtau = 0.0
-    for t in range(steps - 1, -1, -1):
-        r = oracle.step_vjp(states[t], p, gpx, gpy, gvx, gvy)
-        gpx, gpy, gvx, gvy = r["g_px"], r["g_py"], r["g_vx"], r["g_vy"]
-        gprx += r["g_pref_x"]
-        gpry += r["g_pref_y"]
-        gtau += r["g_tau"]
-    gx = vpx.grad.cpu().numpy()
-    gy = vpy.grad.cpu().numpy()
-    print("full-shape rollout gradient rel err:", rel(gx, gprx), rel(gy, gpry), tau.grad.item(),
-          gtau, flush=True)
-    assert rel(gx, gprx) <= 1e-3 and rel(gy, gpry) <= 1e-3
-    assert abs(tau.grad.item() - gtau) <= 1e-3 * abs(gtau)
+    e, exempt = _rollout_vs_chain(sc, sc.steps, 10, "rollout 16384 x 50")
+    assert (e[~exempt] <= 1e-3).all()

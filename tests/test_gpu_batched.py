@@ -56,19 +56,44 @@ def test_batched_equals_single_scene_steps(mode):
         assert torch.equal(status[a:z], st1), s
 
 
+def _batch_result(out, status):
+    g = {k: getattr(out, k).cpu().numpy() for k in ("px", "py", "vx", "vy")}
+    g["status"] = status.cpu().numpy()
+    return g
+
+
+def _contract_per_scene(cat, off, prm, g, scenes, label):
+    """The full parity contract (tests/parity.py) on the given scenes of a
+    batch result g."""
+    for s in scenes:
+        a, z = int(off[s]), int(off[s + 1])
+        if z == a:
+            continue
+        part = {k: v[a:z] for k, v in cat.items()}
+        rep, _, _ = compare_step(part, prm[s], gpu={k: v[a:z] for k, v in g.items()})
+        print(" ", label, "scene", int(s), rep, flush=True)
+
+
 def test_batched_matches_oracle_per_scene():
     import torch
     from paper_2008_11578_amd import orca
     sizes = [64, 500, 3000, 128, 1500]
     parts, prm, off, cat = _batch(sizes, seed=20)
     st = orca.State.from_arrays(cat)
-    out = orca.step_batched(st, orca.Batch(off, prm), orca.Workspace(st.n, n_scenes=len(sizes)))
+    status = torch.zeros(st.n, dtype=torch.uint8, device="cuda")
+    out = orca.step_batched(st, orca.Batch(off, prm), orca.Workspace(st.n, n_scenes=len(sizes)),
+                            status=status)
     torch.cuda.synchronize()
+    g = _batch_result(out, status)
+    # the oracle's batched form equals its per-scene steps ...
     ob = oracle.step_batched(cat, off, prm)
-    dv = np.hypot(out.vx.cpu().numpy() - ob["vx"], out.vy.cpu().numpy() - ob["vy"])
-    # conditioning classes are handled by the single-scene parity tests; here
-    # the batch must agree with the oracle almost everywhere
-    assert np.mean(dv > V_TOL) < 0.005, (dv.max(), np.sum(dv > V_TOL))
+    # ... and every scene of the GPU batch meets the contract agent by agent
+    _contract_per_scene(cat, off, prm, g, range(len(sizes)), "batch of 5")
+    for s in range(len(sizes)):
+        a, z = int(off[s]), int(off[s + 1])
+        o = oracle.step({k: v[a:z] for k, v in cat.items()}, prm[s])
+        np.testing.assert_array_equal(ob["vx"][a:z], o["vx"])
+        np.testing.assert_array_equal(ob["vy"][a:z], o["vy"])
 
 
 def test_batched_c4_shape_runs_and_flags_nothing():
@@ -77,17 +102,32 @@ def test_batched_c4_shape_runs_and_flags_nothing():
     sc = scenarios.c4_batched(n_scenes=64)
     st = orca.State.from_arrays(sc)
     b = orca.Batch(sc.scene_off, sc.scene_params)
-    out = orca.step_batched(st, b, orca.Workspace(st.n, n_scenes=64))
+    status = torch.zeros(st.n, dtype=torch.uint8, device="cuda")
+    out = orca.step_batched(st, b, orca.Workspace(st.n, n_scenes=64), status=status)
     torch.cuda.synchronize()
     assert int(b.error.item()) == 0
     assert torch.isfinite(out.vx).all() and torch.isfinite(out.px).all()
-    # spot-check three scenes against the oracle
-    for s in (0, 31, 63):
-        a, z = sc.scene_off[s], sc.scene_off[s + 1]
-        part = {k: getattr(sc, k)[a:z] for k in oracle._STATE + ("cls",)}
-        o = oracle.step(part, sc.scene_params[s])
-        dv = np.hypot(out.vx[a:z].cpu().numpy() - o["vx"], out.vy[a:z].cpu().numpy() - o["vy"])
-        assert np.mean(dv > V_TOL) < 0.01
+    # three scenes (the first, a middle and the last) under the full contract
+    _contract_per_scene(as_dict(sc), sc.scene_off, sc.scene_params, _batch_result(out, status),
+                        (0, 31, 63), "c4 x64")
+
+
+def _c4_full_check(sc, prm, st, g, label):
+    """Every agent of a 512-scene batch result g (from state st) against the
+    oracle's batched step; the full contract on every scene that holds an
+    agent outside the tolerance, on the three largest scenes and on three
+    others."""
+    S = len(prm)
+    cat = {k: v for k, v in st.items()}
+    ob = oracle.step_batched(cat, sc.scene_off, prm)
+    dv = np.hypot(g["vx"] - ob["vx"], g["vy"] - ob["vy"])
+    print(" ", label, "oracle: max dv", float(dv.max()), "over tolerance",
+          int(np.sum(dv > V_TOL)), flush=True)
+    assert np.mean(dv > V_TOL) < 1e-5
+    sizes = np.diff(sc.scene_off)
+    outside = np.searchsorted(sc.scene_off, np.nonzero(dv > V_TOL)[0], side="right") - 1
+    sample = sorted(set(np.argsort(sizes)[-3:].tolist() + [0, S // 2, S - 1] + outside.tolist()))
+    _contract_per_scene(cat, sc.scene_off, prm, g, sample, label)
 
 
 @pytest.mark.parametrize("block", [64, 256])
@@ -112,13 +152,7 @@ def test_batched_c4_full_in_measured_configuration(block):
     g["status"] = status.cpu().numpy()
     print("c4 full", S, "scenes", st.n, "agents, block", block, flush=True)
 
-    # every agent against the oracle's batched step
     cat = as_dict(sc)
-    ob = oracle.step_batched(cat, sc.scene_off, prm)
-    dv = np.hypot(g["vx"] - ob["vx"], g["vy"] - ob["vy"])
-    print("  oracle: max dv", float(dv.max()), "over tolerance", int(np.sum(dv > V_TOL)),
-          flush=True)
-    assert np.mean(dv > V_TOL) < 1e-5
 
     # every scene equals its plain step
     for s in range(S):
@@ -131,16 +165,48 @@ def test_batched_c4_full_in_measured_configuration(block):
             assert torch.equal(getattr(out, k)[a:z], getattr(o1, k)), (s, k)
         assert torch.equal(status[a:z], st1), s
 
-    # the full contract (conditioning, valid answers) on a sample of scenes
-    # and on every scene that holds an agent outside the tolerance
-    sizes = np.diff(sc.scene_off)
-    outside = np.searchsorted(sc.scene_off, np.nonzero(dv > V_TOL)[0], side="right") - 1
-    sample = sorted(set(np.argsort(sizes)[-3:].tolist() + [0, S // 2, S - 1] + outside.tolist()))
-    for s in sample:
-        a, z = int(sc.scene_off[s]), int(sc.scene_off[s + 1])
-        part = {k: v[a:z] for k, v in cat.items()}
-        rep, _, _ = compare_step(part, prm[s], gpu={k: v[a:z] for k, v in g.items()})
-        print("  scene", int(s), rep, flush=True)
+    # every agent against the oracle, the full contract where it is needed
+    _c4_full_check(sc, prm, cat, g, f"c4 full block {block}")
+
+
+def test_batched_c4_graph_resync():
+    """The 512-scene batch advanced by a captured 50-step graph in the
+    measured launch configuration (cells of R_n / 2, persistent form, 64
+    lanes, capacity 16, one workspace kept across steps): after 0, 50 and 100
+    steps, one batched step from the graph's state with the kept workspace,
+    every agent against the oracle (trajectories are never compared: FP32
+    and FP64 separate chaotically, so both sides restart from the GPU's
+    state)."""
+    import torch
+    from paper_2008_11578_amd import orca
+    sc = scenarios.c4_batched()
+    S = len(sc.scene_params)
+    prm = [dataclasses.replace(p, cell_size=0.5 * p.neighbor_dist) for p in sc.scene_params]
+    b = orca.Batch(sc.scene_off, prm, mode=0, block=64, k_tile=16)
+    a = orca.State.from_arrays(sc)
+    z = a.clone()
+    ws = orca.Workspace(a.n, n_scenes=S)
+    status = torch.zeros(a.n, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(graph, stream=stream):
+            x, y = a, z
+            for _ in range(50):
+                orca.step_batched(x, b, ws, out=y)
+                x, y = y, x
+    torch.cuda.synchronize()
+    assert x is a  # an even number of steps ends where it started
+    for done in (0, 50, 100):
+        if done:
+            graph.replay()
+            torch.cuda.synchronize()
+        snap = a.to_numpy()
+        out = orca.step_batched(a, b, ws, out=z, status=status)
+        torch.cuda.synchronize()
+        assert int(b.error.item()) == 0
+        _c4_full_check(sc, prm, snap, _batch_result(out, status), f"c4 graph after {done}")
 
 
 def test_batched_kept_distances_change_no_result_full_size():

@@ -124,41 +124,94 @@ def test_step_dense_crossing_small():
     _print("step crossing 16k t=0", rep)
 
 
-def test_step_c3_full_in_bench_configuration():
-    """The 1,048,576-agent dense crossing with 0.6 m cells, stepped the way
-    the throughput measurement steps it (one workspace kept across steps, so
-    every step after the first narrows its counting pass by the previous
-    K-th neighbour distance): every agent of the steps that open (after 10
-    steps) and close (after 110) the timed window, and of two in between,
-    against the oracle.  After 27 steps a pair touches to within 5e-10 m,
-    which FP32 takes for an overlap."""
-    import dataclasses
+def _kept_run_checks(sc, params, targets, label, want_lp3=True):
+    """Steps the scene the way the throughput measurement steps it (one
+    workspace kept across steps, so every step after the first narrows its
+    counting pass by the previous K-th neighbour distances).  At each target
+    state the step is taken through orca_step_nbr, which also exports the
+    neighbour lists this step selected: the lists must equal the oracle's
+    exact lists bit for bit and every agent must meet the velocity contract.
+    The checked step continues the run."""
     import torch
     from paper_2008_11578_amd import orca
-    sc = scenarios.c3_crossing()
-    params = dataclasses.replace(sc.params, cell_size=0.6)
     state = orca.State.from_arrays(sc)
     nxt = state.clone()
     ws = orca.Workspace(state.n)
     status = torch.zeros(state.n, dtype=torch.uint8, device="cuda")
     done = 0
-    for target in (10, 27, 60, 110):
+    for target in targets:
         while done < target:
             orca.step(state, params, ws, out=nxt, status=status)
             state, nxt = nxt, state
             done += 1
         torch.cuda.synchronize()
         snap = state.to_numpy()
-        orca.step(state, params, ws, out=nxt, status=status)
+        _, nb, cn = orca.step_nbr(state, params, ws, out=nxt, status=status)
         torch.cuda.synchronize()
+        onb, ocn = oracle.knn(snap["px"], snap["py"], params.neighbor_dist,
+                              params.max_neighbors)
+        np.testing.assert_array_equal(cn.cpu().numpy(), ocn)
+        np.testing.assert_array_equal(nb.cpu().numpy(), onb)
         g = {k: getattr(nxt, k).cpu().numpy() for k in ("px", "py", "vx", "vy")}
         g["status"] = status.cpu().numpy()
         rep, _, _ = compare_step(snap, params, gpu=g)
-        _print("step c3 1M after", target, "steps", rep)
-        assert rep["lp3_gpu"] > 0
-        # the step taken for the check continues the run
+        _print(label, "after", target, "steps: lists exact;", rep)
+        if want_lp3:
+            assert rep["lp3_gpu"] > 0
         state, nxt = nxt, state
         done += 1
+
+
+def test_step_c3_full_in_bench_configuration():
+    """The 1,048,576-agent dense crossing with 0.6 m cells, stepped as
+    measured: the neighbour lists the step selected with its kept distances
+    and every agent's velocity, against the oracle, at the steps that open
+    (after 10 steps) and close (after 110) the timed window and two in
+    between.  After 27 steps a pair touches to within 5e-10 m, which FP32
+    takes for an overlap."""
+    import dataclasses
+    sc = scenarios.c3_crossing()
+    params = dataclasses.replace(sc.params, cell_size=0.6)
+    _kept_run_checks(sc, params, (10, 27, 60, 110), "step c3 1M")
+
+
+def test_step_c2_kept_workspace_resync():
+    """The mixed crowd (65,536 pedestrians, 1,024 vehicles) over its whole
+    200-step run with one kept workspace: the step's own lists and every
+    agent's velocity at the start, the middle and the end."""
+    sc = scenarios.c2_mixed()
+    _kept_run_checks(sc, sc.params, (0, 100, 200), "step c2")
+
+
+def test_step_vehicle_share_half_kept_workspace():
+    """The mixed geometry with half of the 66,560 agents vehicles (nearly
+    every agent on the least-penetration fallback): lists and velocities at
+    the first step and after 20 kept-workspace steps."""
+    sc = scenarios.c2_vehicle_share(0.5)
+    _kept_run_checks(sc, sc.params, (0, 20), "step vehicle share 0.5")
+
+
+def test_step_nbr_equals_step():
+    """orca_step_nbr takes the same step as orca_step (outputs, status and
+    the distances kept for the next step), bit for bit, on a kept workspace."""
+    import torch
+    from paper_2008_11578_amd import orca
+    sc = scenarios.random_state(30000, 100.0, seed=14, n_vehicles=600)
+    st = orca.State.from_arrays(sc)
+    ws = orca.Workspace(st.n)
+    for _ in range(3):
+        orca.step(st, sc.params, ws, out=st)
+    ws2 = orca.Workspace(st.n)
+    ws2.buf.copy_(ws.buf)
+    s1 = torch.zeros(st.n, dtype=torch.uint8, device="cuda")
+    s2 = torch.zeros_like(s1)
+    a = orca.step(st, sc.params, ws, status=s1)
+    b, nb, cn = orca.step_nbr(st, sc.params, ws2, status=s2)
+    torch.cuda.synchronize()
+    for k in ("px", "py", "vx", "vy"):
+        assert torch.equal(getattr(a, k), getattr(b, k)), k
+    assert torch.equal(s1, s2)
+    assert torch.equal(ws.buf, ws2.buf)
 
 
 def test_kept_distances_change_no_result_full_size():
@@ -276,11 +329,13 @@ def test_step_large_coordinates_and_small_workspace():
     # a workspace with very few cells forces the device to enlarge the cells
     s = orca.State.from_arrays(st)
     ws = orca.Workspace(s.n, max_cells=16)
-    out = orca.step(s, sc.params, ws)
+    stat = torch.zeros(s.n, dtype=torch.uint8, device="cuda")
+    out = orca.step(s, sc.params, ws, status=stat)
     torch.cuda.synchronize()
-    o = oracle.step(st, sc.params)
-    dv = np.hypot(out.vx.cpu().numpy() - o["vx"], out.vy.cpu().numpy() - o["vy"])
-    assert np.quantile(dv, 0.99) < 1e-4
+    g = {k: getattr(out, k).cpu().numpy() for k in ("px", "py", "vx", "vy")}
+    g["status"] = stat.cpu().numpy()
+    rep, _, _ = compare_step(st, sc.params, gpu=g)
+    _print("large coordinates, 16 cells", rep)
     nb, cn = orca.build_grid(s, sc.params, ws)
     onb, ocn = oracle.knn(st["px"], st["py"], sc.params.neighbor_dist, sc.params.max_neighbors)
     np.testing.assert_array_equal(nb.cpu().numpy(), onb)

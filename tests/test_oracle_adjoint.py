@@ -288,3 +288,38 @@ def test_full_shape_rollout_gradient_matches_central_differences(oracle_mod):
     assert e_pref.max() <= 1e-3
     assert len(per_an) >= 45 and e_step.max() <= 1e-3
     assert e_tau <= 1e-2
+
+
+def test_rollout_tau_gradient_matches_central_differences(oracle_mod):
+    """The whole-rollout tau derivative at 1e-3 of FP64 central differences,
+    on a shape where a trace-stable difference step exists: 4,096 agents of
+    the rollout workload's density, 20 steps.  Steps h whose +-h rollouts
+    change any neighbour set, branch or active set are skipped (at 1e-7 and
+    above they do); every trace-stable one must agree."""
+    sc = scenarios.c5_rollout(n=4096, side=120.0)
+    prm = sc.params
+    steps = 20
+    st = {k: np.array(getattr(sc, k), dtype=np.uint8 if k == "cls" else np.float64)
+          for k in ("px", "py", "vx", "vy", "pref_x", "pref_y", "radius", "max_speed", "cls")}
+    res = oracle_mod.rollout_grad(st, prm, steps, sc.target_x, sc.target_y)
+    tr0 = oracle_mod.rollout(st, prm, steps)["trace"]
+
+    def dloss(a, b, width):
+        d = ((a["px"] - b["px"]) * (a["px"] + b["px"] - 2 * sc.target_x)
+             + (a["py"] - b["py"]) * (a["py"] + b["py"] - 2 * sc.target_y))
+        return float(np.mean(d)) / width
+
+    tau = float(F32(prm.time_horizon))
+    errs = {}
+    for ht in (1e-7, 3e-8, 1e-8, 3e-9):
+        op_p = oracle_mod.make_params(prm)
+        op_p.tau = tau + ht
+        op_m = oracle_mod.make_params(prm)
+        op_m.tau = tau - ht
+        a, b = oracle_mod.rollout(st, op_p, steps), oracle_mod.rollout(st, op_m, steps)
+        if a["trace"] == tr0 and b["trace"] == tr0:
+            fd = dloss(a, b, 2 * ht)
+            errs[ht] = abs(res["g_tau"] - fd) / abs(fd)
+    print("rollout tau derivative", res["g_tau"], "trace-stable FD errors", errs)
+    assert len(errs) >= 2
+    assert max(errs.values()) <= 1e-3
