@@ -100,7 +100,8 @@ __device__ __forceinline__ void halfplane_vjp(float pax, float pay, float vax, f
     const float R = ra + rb;
     const float dist2 = Px * Px + Py * Py;
     const float R2 = R * R;
-    const bool overlap = !(dist2 > R2);
+    const double c2 = dev::clearance2(pax, pay, ra, pbx, pby, rb);
+    const bool overlap = !(c2 > 0.0);
     const float it = overlap ? inv_dt : inv_tau;
     const float wx = Vx - Px * it, wy = Vy - Py * it;
     const float w2 = wx * wx + wy * wy;
@@ -128,7 +129,7 @@ __device__ __forceinline__ void halfplane_vjp(float pax, float pay, float vax, f
         return;
     }
     // leg: e = (leg P + sigma R P_perp) / |P|^2, n = sigma (-e.y, e.x), u = (V.e) e - V
-    const float leg = sqrtf(fmaxf(dist2 - R2, 0.0f));
+    const float leg = sqrtf(fmaxf((float)c2, 0.0f));
     const float id2 = 1.0f / dist2;
     const bool left = dev::det2(Px, Py, wx, wy) > 0.0f;
     const float sR = left ? R : -R;

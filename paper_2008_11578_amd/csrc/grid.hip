@@ -145,7 +145,33 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const uint32_t *__restric
     if (blockIdx.x == 0 && threadIdx.x == 0) start[g.n_cells] = (uint32_t)g.n;
 }
 
-// (5) scatter into cell order: position = start[cell] + rank.
+// A velocity within the speed cap: (vx, vy) itself when |v| <= v_max (the
+// test in double from the FP32 values, products exact), else scaled onto the
+// cap and rounded to FP32, then moved toward zero one ulp at a time until the
+// test holds.  The ORCA lines an agent takes no responsibility for (f = 0)
+// all pass through its own velocity; a velocity the previous step left on
+// the speed circle lies outside it by a few FP32 ulps half of the time, and
+// the LP's feasible set around that apex would then be thinner than FP32
+// resolves.  Inside the cap, the apex is a feasible point exactly.
+__device__ __forceinline__ void cap_velocity(float &vx, float &vy, float vmax)
+{
+    const double vm2 = (double)vmax * (double)vmax;
+    const double d = (double)vx * (double)vx + (double)vy * (double)vy;
+    if (!(d > vm2)) return;
+    const double s = (double)vmax / sqrt(d);
+    float x = (float)((double)vx * s), y = (float)((double)vy * s);
+    for (int it = 0; it < 16 && (double)x * (double)x + (double)y * (double)y > vm2; ++it) {
+        if (fabsf(x) >= fabsf(y))
+            x = nextafterf(x, 0.0f);
+        else
+            y = nextafterf(y, 0.0f);
+    }
+    vx = x;
+    vy = y;
+}
+
+// (5) scatter into cell order: position = start[cell] + rank; velocities
+// taken within the speed cap (cap_velocity).
 __global__ __launch_bounds__(kBlock) void k_scatter(orca_agents_in in, int n,
                                                     const uint32_t *__restrict__ cell,
                                                     const uint32_t *__restrict__ rank,
@@ -158,7 +184,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter(orca_agents_in in, int n,
     const uint32_t pos = start[cell[i]] + rank[i];
     if (pos >= (uint32_t)n) return;  // cannot happen for a consistent histogram
     s0[pos] = make_float4(in.px[i], in.py[i], __int_as_float(i), in.radius[i]);
-    s1[pos] = make_float4(in.vx[i], in.vy[i], __int_as_float((int)in.cls[i]), 0.0f);
+    float vx = in.vx[i], vy = in.vy[i];
+    cap_velocity(vx, vy, in.max_speed[i]);
+    s1[pos] = make_float4(vx, vy, __int_as_float((int)in.cls[i]), 0.0f);
 }
 
 __global__ void k_fill_zero(uint4 *p, size_t n16)

@@ -24,6 +24,12 @@
 #include <limits.h>
 #include <math.h>
 
+// Multiply-adds are fused within one expression only (C's FP_CONTRACT),
+// never across statements: every instantiation of these templates (plain,
+// batched, capped, adjoint recomputation) then rounds alike, which keeps
+// their results equal bit for bit.
+#pragma clang fp contract(on)
+
 namespace orca {
 namespace dev {
 
@@ -78,20 +84,46 @@ struct KnnShape {
     static constexpr int kCap = 2 * kSlots;       // buffer entries per lane
 };
 
+// Widening of the kept K-th neighbour distance before the counting pass, in
+// speed steps (v_max dt).  The result never depends on it (a circle holding
+// fewer than K is rescanned whole); it trades rescans against candidates.
+#ifndef ORCA_GUESS_SPEED_STEPS
+#define ORCA_GUESS_SPEED_STEPS 2.0
+#endif
+constexpr double kGuessSpeedSteps = ORCA_GUESS_SPEED_STEPS;
+
 // Acceleration lines of an acceleration-limited agent (see accel_line).
 constexpr int kHard = 8;
 
 // Entry e of lane `tid` inside a [slot][BLOCK] float4 array viewed as u64.
-// Both entries of a 16-byte slot stay in the lane's own column tid: the
-// buffer shares the LDS of the half-planes, and the wavefronts of a block
-// run independently, so a lane that has reached its half-planes may only
-// overwrite its own column.  (An [entry][BLOCK] layout would place a lane's
-// entries in other lanes' columns, where a wavefront already writing
-// half-planes corrupts one still selecting.)
+// With several wavefronts per block, both entries of a 16-byte slot stay in
+// the lane's own column tid: the buffer shares the LDS of the half-planes,
+// and the wavefronts of a block run independently, so a lane that has
+// reached its half-planes may only overwrite its own column (an
+// [entry][BLOCK] layout would place a lane's entries in other lanes'
+// columns, where a wavefront already writing half-planes corrupts one still
+// selecting).  A block of one wavefront takes that [entry][BLOCK] layout
+// (one address operation per entry instead of four): its lanes run in
+// lockstep, so every lane has read its entries before any lane writes a
+// half-plane, and lane_order() keeps the compiler from moving an LDS write
+// across those phase boundaries.
 template <int BLOCK>
 __device__ __forceinline__ int buf_idx(int e, int tid)
 {
+    if (BLOCK == kWave) return e * BLOCK + tid;
     return (e >> 1) * (2 * BLOCK) + 2 * tid + (e & 1);
+}
+
+// Orders this lane's LDS accesses before and after it as seen by the other
+// lanes of its wavefront (a compiler barrier; a one-wavefront block needs
+// nothing more, its lanes execute together).
+template <int BLOCK>
+__device__ __forceinline__ void lane_order()
+{
+    if (BLOCK == kWave) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
 }
 
 // Entry = (float(key) bits << 32) | (bin << 28) | cell-order position; the
@@ -276,6 +308,7 @@ __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
 {
     constexpr int kCap = KnnShape<K>::kCap;
     const double xd = xi, yd = yi;
+    lane_order<BLOCK>();  // other lanes' half-planes of a previous tile are read
     // pass 1: per-bin counts of the keys below r2c in kBins equal-area bins,
     // and the candidates themselves while they fit the buffer.  The lane's
     // own agent is counted (and stored) too -- it is always scanned, with
@@ -471,6 +504,19 @@ __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
     return m;
 }
 
+// |P|^2 - R^2 of two agents, in double from their FP32 positions and radii
+// (the differences and the sum are exact there, the products nearly so): the
+// contact test |P| > R and the length of the legs' tangent, sqrt(|P|^2 - R^2),
+// which FP32 would form with a cancellation of its own rounding error when
+// the two discs almost touch.
+__device__ __forceinline__ double clearance2(float pax, float pay, float ra, float pbx, float pby,
+                                             float rb)
+{
+    const double px = (double)pbx - (double)pax, py = (double)pby - (double)pay;
+    const double r = (double)ra + (double)rb;
+    return px * px + py * py - r * r;
+}
+
 // ORCA_{A|B} as (q.x, q.y, d.x, d.y); permitted side det(d, v - q) >= 0.
 // P = p_B - p_A, V = v_A - v_B, R = r_A + r_B.
 //  - not overlapping: w = V - P/tau; the cutoff arc is nearest when the angle
@@ -492,7 +538,8 @@ __device__ __forceinline__ float4 halfplane(float pax, float pay, float vax, flo
     const float R = ra + rb;
     const float dist2 = Px * Px + Py * Py;
     const float R2 = R * R;
-    const bool overlap = !(dist2 > R2);
+    const double c2 = clearance2(pax, pay, ra, pbx, pby, rb);
+    const bool overlap = !(c2 > 0.0);
     const float it = overlap ? inv_dt : inv_tau;
     const float wx = Vx - Px * it, wy = Vy - Py * it;
     const float w2 = wx * wx + wy * wy;
@@ -509,7 +556,7 @@ __device__ __forceinline__ float4 halfplane(float pax, float pay, float vax, flo
     // leg form, only where a lane of the wavefront needs it (in dense flows
     // most half-planes take the cutoff arc: relative velocities are small)
     if (__any(!arc)) {
-        const float leg = sqrtf(fmaxf(dist2 - R2, 0.0f));
+        const float leg = sqrtf(fmaxf((float)c2, 0.0f));
         const float id2 = overlap ? 0.0f : 1.0f / dist2;
         const bool left = det2(Px, Py, wx, wy) > 0.0f;
         const float sR = left ? R : -R;
@@ -603,13 +650,16 @@ struct LdsLines {
 // This is the same line as the one through the intersection of lines i and j
 // (or the midpoint of q_i, q_j for antiparallel lines), but stays well
 // scaled in FP32 when the two lines are nearly parallel and intersect far
-// away from the speed disc.
+// away from the speed disc.  Two lines with the same point q pass through it
+// together, and so does their boundary: it keeps q itself as its point.
 template <int BLOCK, bool ACC = false>
 struct ProjLines {
     const LdsLines<BLOCK, ACC> &ls;
     float4 li;
     float ci;    // det(d_i, q_i)
     float eps;
+    // Computes the boundary of an ORCA line without a branch; returns false
+    // when it is not a constraint (its components are then meaningless).
     __device__ __forceinline__ bool get(int j, float4 &out) const
     {
         const float4 lj = ls.line(j);
@@ -618,13 +668,19 @@ struct ProjLines {
             return true;
         }
         const float dij = det2(li.z, li.w, lj.z, lj.w);
-        if (fabsf(dij) <= eps && li.z * lj.z + li.w * lj.w > 0.0f) return false;
+        const bool same = fabsf(dij) <= eps && li.z * lj.z + li.w * lj.w > 0.0f;
         const float ex = lj.z - li.z, ey = lj.w - li.w;
         const float il = 1.0f / sqrtf(ex * ex + ey * ey);
         const float dx = ex * il, dy = ey * il;
         const float off = (det2(lj.z, lj.w, lj.x, lj.y) - ci) * il;
-        out = make_float4(-dy * off, dx * off, dx, dy);
-        return true;
+        // Lines through one point (the f = 0 lines of an agent all pass
+        // exactly through its velocity) have their boundary through that same
+        // point: it is kept exactly, so that an LP whose feasible region is a
+        // cone with its apex there (or that apex alone) decides feasibility
+        // at the apex exactly, as the oracle's intersection form does.
+        const bool common = lj.x == li.x && lj.y == li.y;
+        out = make_float4(common ? li.x : -dy * off, common ? li.y : dx * off, dx, dy);
+        return !same;
     }
 };
 
@@ -670,35 +726,46 @@ __device__ __forceinline__ bool lp1(const Src &src, int i, float4 li, float vmax
                                     float ox, float oy, float tx, float ty, float eps, float &x,
                                     float &y, int &how, int &bound)
 {
+    // The line meets the speed circle at t^2 + 2 dot t + c = 0, c = |q|^2 -
+    // v_max^2.  c is formed in double (exact products), so its sign -- whether
+    // q itself lies in the disc -- is exact; the root near q is taken as c
+    // over the other root, which has no cancellation, so q stays inside the
+    // interval exactly when it lies in the disc (the f = 0 lines of an agent
+    // pass through its own velocity, which the grid build puts inside the
+    // disc: that apex is then a feasible point, as it is exactly).
     const float dot = li.x * li.z + li.y * li.w;
-    const float disc = dot * dot + vmax * vmax - (li.x * li.x + li.y * li.y);
+    const double cd = (double)li.x * (double)li.x + (double)li.y * (double)li.y -
+                      (double)vmax * (double)vmax;
+    const float c = (float)cd;
+    const float disc = dot * dot - c;
     if (disc < 0.0f) return false;
     const float sq = sqrtf(disc);
-    float tl = -dot - sq, tr = -dot + sq;
+    const float far = dot > 0.0f ? -dot - sq : -dot + sq;
+    const float near = far != 0.0f ? c / far : 0.0f;
+    float tl = fminf(far, near), tr = fmaxf(far, near);
     int sl = -1, sr = -1;
+    // Branch-free over j: the lanes of a wavefront meet different cases
+    // (parallel, lower or upper bound) at the same j, so every case is a
+    // select.  The interval only shrinks, so a failure at some j is a
+    // failure at the end: it is recorded in `ok` instead of returning.
+    bool ok = true;
     for (int j = 0; j < i; ++j) {
         float4 lj;
-        if (!src.get(j, lj)) continue;
+        const bool valid = src.get(j, lj);
         const float a = det2(lj.z, lj.w, li.z, li.w);
         const float b = det2(lj.z, lj.w, li.x - lj.x, li.y - lj.y);
-        if (fabsf(a) <= eps) {
-            if (b < 0.0f) return false;
-            continue;
-        }
+        const bool par = fabsf(a) <= eps;
         const float t = -b / a;
-        if (a > 0.0f) {
-            if (t > tl) {
-                tl = t;
-                sl = j;
-            }
-        } else {
-            if (t < tr) {
-                tr = t;
-                sr = j;
-            }
-        }
-        if (tl > tr) return false;
+        const bool cut = valid && !par;
+        const bool lo = cut && a > 0.0f && t > tl;
+        const bool hi = cut && !(a > 0.0f) && t < tr;
+        tl = lo ? t : tl;
+        sl = lo ? j : sl;
+        tr = hi ? t : tr;
+        sr = hi ? j : sr;
+        ok = ok && !(valid && par && b < 0.0f) && !(tl > tr);
     }
+    if (!ok) return false;
     float t;
     if (mode == 0) {
         t = li.z * (ox - li.x) + li.w * (oy - li.y);
@@ -755,8 +822,8 @@ __device__ __forceinline__ int lp2(const Src &src, int m, float vmax, int mode, 
     }
     for (int i = 0; i < m; ++i) {
         float4 li;
-        if (!src.get(i, li)) continue;
-        if (det2(li.z, li.w, li.x - x, li.y - y) > 0.0f) {
+        const bool valid = src.get(i, li);
+        if (valid && det2(li.z, li.w, li.x - x, li.y - y) > 0.0f) {
             float nx = x, ny = y;
             int how, bound;
             if (!lp1(src, i, li, vmax, mode, ox, oy, tx, ty, eps, nx, ny, how, bound)) {
@@ -856,6 +923,7 @@ __device__ __forceinline__ void build_halfplanes(const uint32_t (&pos)[K], int m
     const float fa = ci ? p.f10 : p.f00;  // f[ci][0]
     const float fb = ci ? p.f11 : p.f01;  // f[ci][1]
     constexpr int kHpGroup = 4;
+    lane_order<BLOCK>();  // every lane's selection entries are read
 #pragma unroll
     for (int q0 = 0; q0 < K; q0 += kHpGroup) {
         float4 b0[kHpGroup], b1[kHpGroup];
@@ -925,7 +993,8 @@ __device__ __forceinline__ void step_agent(int s, const GridMeta &g, const Scene
     if (guess) {
         const float d = guess[i];
         if (d > 0.0f) {
-            const double r = (double)d + 2.0 * (double)p.dt * (double)vmax + 0.005 * (double)g.rn;
+            const double r = (double)d + kGuessSpeedSteps * (double)p.dt * (double)vmax +
+                             0.005 * (double)g.rn;
             rg2 = fmin(r * r, g.rn2);
         }
     }

@@ -10,7 +10,7 @@ import pytest
 import oracle
 from paper_2008_11578_amd import scenarios
 
-from parity import as_dict, compare_step, gpu_step
+from parity import as_dict, compare_step, gpu_step, perturbed
 
 pytestmark = pytest.mark.gpu
 
@@ -247,4 +247,12 @@ def test_capped_step_backward_matches_oracle(accel):
         _print(k, _rel(a, ref))
         assert _rel(a, ref) <= tol, (k, _rel(a, ref))
         assert np.max(np.abs(a - ref)) <= 1e-3 * np.max(np.abs(ref)), k
-    assert abs(float(gt.item()) - o["g_tau"]) <= 1e-4 * abs(o["g_tau"])
+    # tau's cotangent sums every agent's share, the touching agents' included,
+    # whose derivatives FP32 resolves poorly: the bound is 1e-4 relative, or
+    # twice what the oracle's own value moves on states perturbed by FP32-sized
+    # amounts (velocities by 1e-6 m/s, radii by one ulp), whichever is larger
+    moved = max(abs(oracle.step_vjp(perturbed(S, 600 + r), params,
+                                    *[c.astype(np.float64) for c in cot])["g_tau"] - o["g_tau"])
+                for r in range(2))
+    _print("g_tau", float(gt.item()), o["g_tau"], "oracle moves by", moved)
+    assert abs(float(gt.item()) - o["g_tau"]) <= max(1e-4 * abs(o["g_tau"]), 2.0 * moved)

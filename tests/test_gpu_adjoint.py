@@ -13,6 +13,8 @@ import pytest
 import oracle
 from paper_2008_11578_amd import scenarios
 
+from parity import perturbed
+
 pytestmark = pytest.mark.gpu
 
 
@@ -152,6 +154,78 @@ def _rollout_vs_chain(sc, steps, ckpt, label):
         s, s2 = s2, s
     fin = s.to_numpy()
     np.testing.assert_array_equal(fin["px"], px.detach().cpu().numpy())
+    g = np.concatenate([vpx.grad.cpu().numpy(), vpy.grad.cpu().numpy()])
+    ref, gtau = _oracle_chain(states, fin, sc, p)
+    e = component_err(g, ref)
+    e_tau = abs(tau.grad.item() - gtau) / abs(gtau)
+    touch = touching(states, p)
+    # conditioning of the FP64 chained gradient itself: the same chain on
+    # states moved by FP32-sized amounts (velocities by 1e-6 m/s, radii by
+    # one ulp, as the step parity contract does); a component that then
+    # moves by more than a tenth of the tolerance depends on an interaction
+    # decided below FP32 resolution (a contact, nearly parallel active
+    # lines), directly or through a neighbour earlier in the rollout
+    sens = np.zeros_like(e)
+    for r in range(2):
+        pert = [perturbed(s_, 4000 + 97 * t + r) for t, s_ in enumerate(states)]
+        ref_p, _ = _oracle_chain(pert, fin, sc, p)
+        sens = np.maximum(sens, component_err(ref_p, ref))
+    ill = sens > 1e-4
+    # agents whose forward step on the GPU took another answer than the
+    # oracle's from the same state (allowed by the step parity contract for
+    # ill-conditioned agents only): their Jacobian there belongs to another
+    # active set, which reaches their own desired velocity and those of the
+    # neighbours their half-planes were built from
+    flip = np.zeros(n, bool)
+    for t in range(steps):
+        nxt_ = states[t + 1] if t + 1 < steps else fin
+        o = oracle.step(states[t], p, want_neighbors=True)
+        bad = np.hypot(o["vx"] - nxt_["vx"], o["vy"] - nxt_["vy"]) > 1e-5
+        if bad.any():
+            flip[bad] = True
+            nb = o["nbr"][bad]
+            flip[nb[nb >= 0]] = True
+    flip2 = np.concatenate([flip, flip])
+    # diagnostics of the components outside the tolerance that none of the
+    # probes explains: the largest one-step velocity difference of the agent
+    # and of its neighbours over the rollout
+    unexpl = np.nonzero((e > 1e-3) & ~ill & ~flip2)[0] % n
+    if unexpl.size:
+        own = np.zeros(n)
+        nbm = np.zeros(n)
+        for t in range(steps):
+            nxt_ = states[t + 1] if t + 1 < steps else fin
+            o = oracle.step(states[t], p, want_neighbors=True)
+            d = np.hypot(o["vx"] - nxt_["vx"], o["vy"] - nxt_["vy"])
+            own = np.maximum(own, d)
+            nb = o["nbr"]
+            nbm = np.maximum(nbm, np.where(nb >= 0, d[np.where(nb >= 0, nb, 0)], 0).max(axis=1))
+        print("  unexplained:", [(int(a), float(own[a]), float(nbm[a])) for a in unexpl[:12]],
+              flush=True)
+    touch2 = np.concatenate([touch, touch])
+    exempt = ill | flip2
+    worst = np.argsort(e)[-5:][::-1]
+    print(f"{label}: {e.size} components, err max {e.max():.2e} median {np.median(e):.2e}, "
+          f"over 1e-3: {int(np.sum(e > 1e-3))} ({int(np.sum((e > 1e-3) & exempt))} "
+          f"ill-conditioned, {int(np.sum((e > 1e-3) & touch2 & ~exempt))} others touching, "
+          f"{int(np.sum((e > 1e-3) & flip2 & ~exempt))} others near a differing step, "
+          f"{int(np.sum((e > 1e-3) & ~flip2 & ~touch2 & ~exempt))} none of these); "
+          f"{int(flip.sum())} agents near a differing step; "
+          f"{int(touch.sum())} agents touch, {int(ill.sum())} components ill-conditioned; "
+          f"tau {tau.grad.item():.6g} vs {gtau:.6g} (err {e_tau:.1e}); worst "
+          f"{[(int(i % n), float(e[i]), float(sens[i]), bool(exempt[i])) for i in worst]}",
+          flush=True)
+    assert rel(g, ref) <= 1e-3
+    assert e_tau <= 1e-3
+    assert exempt.mean() <= 0.2, exempt.mean()
+    return e, exempt
+
+
+def _oracle_chain(states, fin, sc, p):
+    """The oracle's one-step VJPs chained backwards along `states` from the
+    loss gradient at the final positions `fin`: (d loss / d v_pref as
+    [x components, y components], d loss / d tau)."""
+    n = sc.n
     gpx = 2 * (fin["px"].astype(np.float64) - sc.target_x) / n
     gpy = 2 * (fin["py"].astype(np.float64) - sc.target_y) / n
     gvx = np.zeros(n)
@@ -159,27 +233,13 @@ def _rollout_vs_chain(sc, steps, ckpt, label):
     gprx = np.zeros(n)
     gpry = np.zeros(n)
     gtau = 0.0
-    for t in range(steps - 1, -1, -1):
+    for t in range(len(states) - 1, -1, -1):
         r = oracle.step_vjp(states[t], p, gpx, gpy, gvx, gvy)
         gpx, gpy, gvx, gvy = r["g_px"], r["g_py"], r["g_vx"], r["g_vy"]
         gprx += r["g_pref_x"]
         gpry += r["g_pref_y"]
         gtau += r["g_tau"]
-    g = np.concatenate([vpx.grad.cpu().numpy(), vpy.grad.cpu().numpy()])
-    ref = np.concatenate([gprx, gpry])
-    e = component_err(g, ref)
-    e_tau = abs(tau.grad.item() - gtau) / abs(gtau)
-    touch = touching(states, p)
-    exempt = np.concatenate([touch, touch])
-    worst = np.argsort(e)[-5:][::-1]
-    print(f"{label}: {e.size} components, err max {e.max():.2e} median {np.median(e):.2e}, "
-          f"over 1e-3: {int(np.sum(e > 1e-3))} ({int(np.sum((e > 1e-3) & exempt))} touching; "
-          f"{int(touch.sum())} agents touch); tau {tau.grad.item():.6g} vs {gtau:.6g} "
-          f"(err {e_tau:.1e}); worst {[(int(i % n), float(e[i]), bool(exempt[i])) for i in worst]}",
-          flush=True)
-    assert rel(g, ref) <= 1e-3
-    assert e_tau <= 1e-3
-    return e, exempt
+    return np.concatenate([gprx, gpry]), gtau
 
 
 def test_rollout_gradient_matches_oracle_chain():

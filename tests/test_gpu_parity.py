@@ -211,7 +211,19 @@ def test_step_nbr_equals_step():
     for k in ("px", "py", "vx", "vy"):
         assert torch.equal(getattr(a, k), getattr(b, k)), k
     assert torch.equal(s1, s2)
-    assert torch.equal(ws.buf, ws2.buf)
+    # what the workspace carries to the next step (the kept neighbour
+    # distances, its last region) is the same; the cell-ordered copy is not
+    # compared, since the order of agents inside one cell follows the order
+    # of the counting pass's atomic increments and differs between runs
+    assert torch.equal(_kept_distances(ws, st.n), _kept_distances(ws2, st.n))
+
+
+def _kept_distances(ws, n):
+    """The workspace's last region: each agent's K-th neighbour distance
+    kept for the next step (float32, caller order)."""
+    import torch
+    region = (4 * n + 255) // 256 * 256
+    return ws.buf[ws.nbytes - region:ws.nbytes - region + 4 * n].view(torch.float32)
 
 
 def test_kept_distances_change_no_result_full_size():
