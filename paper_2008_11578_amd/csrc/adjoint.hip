@@ -212,7 +212,7 @@ __device__ __forceinline__ void adjoint_agent(int s, const AdjArgs &a, const Gri
     float vx, vy;
     dev::ActiveSet rec{dev::kFree, -1, -1, -1};
     const int mt = nh + m;
-    int fail = dev::lp2<true>(src, mt, vmax, 0, prx, pry, 0.0f, 0.0f, p.eps, vx, vy, &rec);
+    int fail = dev::lp2<true, float>(src, mt, vmax, 0, prx, pry, 0.0f, 0.0f, p.eps, vx, vy, &rec);
     if (ACC && fail < nh) {
         vx = cx;
         vy = cy;

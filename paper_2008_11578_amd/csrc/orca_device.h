@@ -38,6 +38,33 @@ __device__ __forceinline__ float det2(float ax, float ay, float bx, float by)
     return ax * by - ay * bx;
 }
 
+__device__ __forceinline__ double det2(double ax, double ay, double bx, double by)
+{
+    return ax * by - ay * bx;
+}
+
+// The LP runs in float (LP2 over the agent's lines) or in double (LP3's
+// sub-problems): these pick the operation of the scalar type.
+__device__ __forceinline__ float lp_sqrt(float v) { return sqrtf(v); }
+__device__ __forceinline__ double lp_sqrt(double v) { return sqrt(v); }
+__device__ __forceinline__ float lp_abs(float v) { return fabsf(v); }
+__device__ __forceinline__ double lp_abs(double v) { return fabs(v); }
+__device__ __forceinline__ float lp_min(float a, float b) { return fminf(a, b); }
+__device__ __forceinline__ double lp_min(double a, double b) { return fmin(a, b); }
+__device__ __forceinline__ float lp_max(float a, float b) { return fmaxf(a, b); }
+__device__ __forceinline__ double lp_max(double a, double b) { return fmax(a, b); }
+
+template <class S>
+struct LpVec;
+template <>
+struct LpVec<float> {
+    using T = float4;
+};
+template <>
+struct LpVec<double> {
+    using T = double4;
+};
+
 
 
 
@@ -658,8 +685,8 @@ struct ProjLines {
     float4 li;
     float ci;    // det(d_i, q_i)
     float eps;
-    // Computes the boundary of an ORCA line without a branch; returns false
-    // when it is not a constraint (its components are then meaningless).
+    // Computes the boundary without a branch on the line; returns false when
+    // it is not a constraint (its components are then meaningless).
     __device__ __forceinline__ bool get(int j, float4 &out) const
     {
         const float4 lj = ls.line(j);
@@ -680,6 +707,43 @@ struct ProjLines {
         // at the apex exactly, as the oracle's intersection form does.
         const bool common = lj.x == li.x && lj.y == li.y;
         out = make_float4(common ? li.x : -dy * off, common ? li.y : dx * off, dx, dy);
+        return !same;
+    }
+};
+
+
+// The same boundaries in double, for a sub-problem that failed in FP32: the
+// boundary passes through the intersection of lines i and j (the midpoint
+// of q_i and q_j when they are antiparallel) with direction
+// (d_j - d_i) / |d_j - d_i|.  Such a sub-problem always has a solution in
+// exact arithmetic (the current point lies in its region), so its failure
+// means a feasible set thinner than FP32 resolves: several lines through
+// one vertex, the f = 0 lines that all meet at the agent's own velocity, an
+// apex on the speed circle.  In double it is decided as the oracle decides.
+template <int BLOCK, bool ACC = false>
+struct ProjLinesD {
+    const LdsLines<BLOCK, ACC> &ls;
+    double4 li;
+    double eps;
+    // Computes the boundary without a branch on the line; returns false when
+    // it is not a constraint (its components are then meaningless).
+    __device__ __forceinline__ bool get(int j, double4 &out) const
+    {
+        const float4 l = ls.line(j);
+        const double4 lj = make_double4(l.x, l.y, l.z, l.w);
+        if (ACC && j < ls.nh) {
+            out = lj;
+            return true;
+        }
+        const double dij = det2(li.z, li.w, lj.z, lj.w);
+        const bool par = fabs(dij) <= eps;
+        const bool same = par && li.z * lj.z + li.w * lj.w > 0.0;
+        const double t = det2(lj.z, lj.w, li.x - lj.x, li.y - lj.y) / dij;
+        const double px = par ? 0.5 * (li.x + lj.x) : li.x + t * li.z;
+        const double py = par ? 0.5 * (li.y + lj.y) : li.y + t * li.w;
+        const double ex = lj.z - li.z, ey = lj.w - li.w;
+        const double il = 1.0 / sqrt(ex * ex + ey * ey);
+        out = make_double4(px, py, ex * il, ey * il);
         return !same;
     }
 };
@@ -714,6 +778,20 @@ struct ActiveSet {
     int a, b;
 };
 
+// What the LP's scalar type resolves in a velocity, relative to v_max (about
+// 16 ulps): the slack of lp1's feasibility test and the least excess over
+// LP3's level that makes a line be re-solved.
+template <class S>
+struct FeasSlack;
+template <>
+struct FeasSlack<float> {
+    static constexpr float v = 0x1p-20f;
+};
+template <>
+struct FeasSlack<double> {
+    static constexpr double v = 0x1p-49;
+};
+
 // One-dimensional sub-problem on line li (index i): the parameter interval
 // inside the speed disc and on the permitted side of every valid line j < i.
 // mode 0: closest point to (ox, oy); mode 1: extreme along unit (ox, oy), or,
@@ -721,11 +799,12 @@ struct ActiveSet {
 // `how` reports what fixed the result: 0 projection, 1 / 2 the lower / upper
 // end of the interval (bounded by line `src`, or by the disc when src < 0),
 // 3 the tie projection.
-template <class Src>
-__device__ __forceinline__ bool lp1(const Src &src, int i, float4 li, float vmax, int mode,
-                                    float ox, float oy, float tx, float ty, float eps, float &x,
-                                    float &y, int &how, int &bound)
+template <class S, class Src>
+__device__ __forceinline__ bool lp1(const Src &src, int i, typename LpVec<S>::T li, S vmax,
+                                    int mode, S ox, S oy, S tx, S ty, S eps, S &x, S &y, int &how,
+                                    int &bound)
 {
+    using V4 = typename LpVec<S>::T;
     // The line meets the speed circle at t^2 + 2 dot t + c = 0, c = |q|^2 -
     // v_max^2.  c is formed in double (exact products), so its sign -- whether
     // q itself lies in the disc -- is exact; the root near q is taken as c
@@ -733,51 +812,58 @@ __device__ __forceinline__ bool lp1(const Src &src, int i, float4 li, float vmax
     // interval exactly when it lies in the disc (the f = 0 lines of an agent
     // pass through its own velocity, which the grid build puts inside the
     // disc: that apex is then a feasible point, as it is exactly).
-    const float dot = li.x * li.z + li.y * li.w;
+    const S dot = li.x * li.z + li.y * li.w;
     const double cd = (double)li.x * (double)li.x + (double)li.y * (double)li.y -
                       (double)vmax * (double)vmax;
-    const float c = (float)cd;
-    const float disc = dot * dot - c;
-    if (disc < 0.0f) return false;
-    const float sq = sqrtf(disc);
-    const float far = dot > 0.0f ? -dot - sq : -dot + sq;
-    const float near = far != 0.0f ? c / far : 0.0f;
-    float tl = fminf(far, near), tr = fmaxf(far, near);
+    const S c = (S)cd;
+    const S disc = dot * dot - c;
+    if (disc < (S)0) return false;
+    const S sq = lp_sqrt(disc);
+    const S far = dot > (S)0 ? -dot - sq : -dot + sq;
+    const S near = far != (S)0 ? c / far : (S)0;
+    S tl = lp_min(far, near), tr = lp_max(far, near);
     int sl = -1, sr = -1;
     // Branch-free over j: the lanes of a wavefront meet different cases
     // (parallel, lower or upper bound) at the same j, so every case is a
     // select.  The interval only shrinks, so a failure at some j is a
     // failure at the end: it is recorded in `ok` instead of returning.
+    // An interval empty by less than the scalar type resolves at this
+    // velocity scale (FeasSlack v_max) counts as one point: a feasible set
+    // that thin --
+    // several lines through one vertex, an apex on the speed circle -- is
+    // empty or not by rounding alone, and the point found then violates a
+    // constraint by no more than that.
+    const S slack = vmax * FeasSlack<S>::v;
     bool ok = true;
     for (int j = 0; j < i; ++j) {
-        float4 lj;
+        V4 lj;
         const bool valid = src.get(j, lj);
-        const float a = det2(lj.z, lj.w, li.z, li.w);
-        const float b = det2(lj.z, lj.w, li.x - lj.x, li.y - lj.y);
-        const bool par = fabsf(a) <= eps;
-        const float t = -b / a;
+        const S a = det2(lj.z, lj.w, li.z, li.w);
+        const S b = det2(lj.z, lj.w, li.x - lj.x, li.y - lj.y);
+        const bool par = lp_abs(a) <= eps;
+        const S t = -b / a;
         const bool cut = valid && !par;
-        const bool lo = cut && a > 0.0f && t > tl;
-        const bool hi = cut && !(a > 0.0f) && t < tr;
+        const bool lo = cut && a > (S)0 && t > tl;
+        const bool hi = cut && !(a > (S)0) && t < tr;
         tl = lo ? t : tl;
         sl = lo ? j : sl;
         tr = hi ? t : tr;
         sr = hi ? j : sr;
-        ok = ok && !(valid && par && b < 0.0f) && !(tl > tr);
+        ok = ok && !(valid && par && b < -slack) && !(tl > tr + slack);
     }
     if (!ok) return false;
-    float t;
+    S t;
     if (mode == 0) {
         t = li.z * (ox - li.x) + li.w * (oy - li.y);
         how = 0;
     } else {
-        const float sd = ox * li.z + oy * li.w;
-        if (fabsf(sd) <= eps) {
+        const S sd = ox * li.z + oy * li.w;
+        if (lp_abs(sd) <= eps) {
             t = li.z * (tx - li.x) + li.w * (ty - li.y);
             how = 3;
         } else {
-            t = sd > 0.0f ? tr : tl;
-            how = sd > 0.0f ? 2 : 1;
+            t = sd > (S)0 ? tr : tl;
+            how = sd > (S)0 ? 2 : 1;
         }
     }
     if (t < tl) {
@@ -797,20 +883,19 @@ __device__ __forceinline__ bool lp1(const Src &src, int i, float4 li, float vmax
 // Incremental 2D LP over lines 0..m-1 of `src` and the disc |v| <= vmax.
 // Returns the first infeasible line, or m; v keeps its pre-failure value.
 // With REC the active set of the result is written to *rec.
-template <bool REC, class Src>
-__device__ __forceinline__ int lp2(const Src &src, int m, float vmax, int mode, float ox,
-                                   float oy, float tx, float ty, float eps, float &vx, float &vy,
-                                   ActiveSet *rec)
+template <bool REC, class S, class Src>
+__device__ __forceinline__ int lp2(const Src &src, int m, S vmax, int mode, S ox, S oy, S tx,
+                                   S ty, S eps, S &vx, S &vy, ActiveSet *rec)
 {
-    float x, y;
+    S x, y;
     if (mode == 1) {
         x = ox * vmax;
         y = oy * vmax;
         if (REC) rec->kind = kDir;
     } else {
-        const float o2 = ox * ox + oy * oy;
+        const S o2 = ox * ox + oy * oy;
         if (o2 > vmax * vmax) {
-            const float sc = vmax / sqrtf(o2);
+            const S sc = vmax / lp_sqrt(o2);
             x = ox * sc;
             y = oy * sc;
             if (REC) rec->kind = kDisc;
@@ -821,12 +906,12 @@ __device__ __forceinline__ int lp2(const Src &src, int m, float vmax, int mode, 
         }
     }
     for (int i = 0; i < m; ++i) {
-        float4 li;
+        typename LpVec<S>::T li;
         const bool valid = src.get(i, li);
-        if (valid && det2(li.z, li.w, li.x - x, li.y - y) > 0.0f) {
-            float nx = x, ny = y;
+        if (valid && det2(li.z, li.w, li.x - x, li.y - y) > (S)0) {
+            S nx = x, ny = y;
             int how, bound;
-            if (!lp1(src, i, li, vmax, mode, ox, oy, tx, ty, eps, nx, ny, how, bound)) {
+            if (!lp1<S>(src, i, li, vmax, mode, ox, oy, tx, ty, eps, nx, ny, how, bound)) {
                 vx = x;
                 vy = y;
                 return i;
@@ -848,6 +933,7 @@ __device__ __forceinline__ int lp2(const Src &src, int m, float vmax, int mode, 
     return m;
 }
 
+
 // Least penetration (Sec. 3): from LP2's partial result at line `fail`, each
 // later line i whose penetration exceeds the current level re-solves v in the
 // region where no earlier line penetrates more than line i, as deep into line
@@ -861,13 +947,31 @@ __device__ __forceinline__ void lp3(const LdsLines<BLOCK, ACC> &ls, int m, int f
     float level = 0.0f;
     float x = vx, y = vy;
     const int nhard = ACC ? ls.nh : 0;
+    // a line is re-solved only when it exceeds the level by more than FP32
+    // resolves in a penetration (about 2^-20 v_max): at a point where several
+    // lines are penetrated equally, FP32 rounding alone would otherwise
+    // decide whether a later tied line triggers a re-solve, and the re-solve
+    // then jumps to another vertex of the tie
+    const float tol = vmax * FeasSlack<float>::v;
     for (int i = fail > nhard ? fail : nhard; i < m; ++i) {
         const float4 li = ls.line(i);
-        if (det2(li.z, li.w, li.x - x, li.y - y) <= level) continue;
+        if (det2(li.z, li.w, li.x - x, li.y - y) <= level + tol) continue;
         ProjLines<BLOCK, ACC> src{ls, li, det2(li.z, li.w, li.x, li.y), eps};
         float nx = x, ny = y;
         ActiveSet inner;
-        if (lp2<REC>(src, i, vmax, 1, -li.w, li.z, tx, ty, eps, nx, ny, &inner) == i) {
+        bool solved = lp2<REC, float>(src, i, vmax, 1, -li.w, li.z, tx, ty, eps, nx, ny,
+                                      &inner) == i;
+        if (!solved) {
+            // failed in FP32 only: solve it again in double (ProjLinesD)
+            const double4 lid = make_double4(li.x, li.y, li.z, li.w);
+            ProjLinesD<BLOCK, ACC> srcd{ls, lid, (double)eps};
+            double dx = x, dy = y;
+            solved = lp2<REC, double>(srcd, i, (double)vmax, 1, -lid.w, lid.z, (double)tx,
+                                      (double)ty, (double)eps, dx, dy, &inner) == i;
+            nx = (float)dx;
+            ny = (float)dy;
+        }
+        if (solved) {
             x = nx;
             y = ny;
             if (REC) {
@@ -1030,7 +1134,7 @@ __device__ __forceinline__ void step_agent(int s, const GridMeta &g, const Scene
                                    ACC && nh ? accel_half_width(acc, p.dt) : 0.0f};
     const int mt = nh + m;
     float vx, vy;
-    int fail = lp2<false>(src, mt, vmax, 0, prx, pry, 0.0f, 0.0f, p.eps, vx, vy, nullptr);
+    int fail = lp2<false, float>(src, mt, vmax, 0, prx, pry, 0.0f, 0.0f, p.eps, vx, vy, nullptr);
     uint8_t st = 0;
     if (ACC && fail < nh) {
         // the octagon's centre lies in the speed disc, so only rounding can

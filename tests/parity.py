@@ -14,8 +14,12 @@ own half-planes is perturbed by a relative 1e-6 (a few FP32 ulps, the error
 of half-planes formed in FP32) is ill-conditioned as well -- its LP path
 (which line first fails, which interval end binds, which LP3 boundary wins)
 is decided below FP32 resolution.  Such an agent must still hold a valid
-answer to the oracle's FP64 problem (`valid_answer`); these agents are
-counted and their share is bounded.
+answer to the oracle's FP64 problem (`valid_answer`), or match the oracle
+across a contact within rounding (`contact_flipped`), or lie within twice
+the distance the oracle's own answer moves under the two perturbations
+above (`oracle_sensitivity`, `line_movement`: at a vertex of nearly
+parallel lines or a tie of LP3 the answer moves with rounding itself);
+these agents are counted and their share is bounded.
 """
 from __future__ import annotations
 
@@ -102,8 +106,16 @@ def line_sensitive(o, st, idx, params=None, reps=4, rel=1e-6, seed=77):
     """For agents `idx`: whether the oracle LP answer on the agent's own
     lines (acceleration lines, when capped, then half-planes) moves by more
     than COND_TOL when every line component is scaled by (1 + U(-rel, rel))."""
+    return line_movement(o, st, idx, params, reps, rel, seed) > COND_TOL
+
+
+def line_movement(o, st, idx, params=None, reps=4, rel=1e-6, seed=77):
+    """For agents `idx`: the farthest the oracle LP answer on the agent's own
+    lines moves when every line component is scaled by (1 + U(-rel, rel)),
+    a few FP32 ulps: how far FP32 rounding of the half-planes alone can
+    carry the answer."""
     rng = np.random.default_rng(seed)
-    out = np.zeros(len(idx), bool)
+    out = np.zeros(len(idx))
     vmax = np.asarray(st["max_speed"], np.float64)
     for k, a in enumerate(idx):
         m = int(o["cnt"][a])
@@ -123,7 +135,7 @@ def line_sensitive(o, st, idx, params=None, reps=4, rel=1e-6, seed=77):
         for _ in range(reps):
             v1 = solve(lines * (1.0 + rng.uniform(-rel, rel, size=lines.shape)))
             worst = max(worst, float(np.hypot(*(v1 - v0))))
-        out[k] = worst > COND_TOL
+        out[k] = worst
     return out
 
 
@@ -221,10 +233,14 @@ def compare_step(state_np, params, *, require_all=False, max_ill_frac=0.01, reps
     if bad.any() and not require_all:
         sens = oracle_sensitivity(st, params, o, reps=reps)
         ill = sens > COND_TOL
-        cand = np.nonzero(bad & ~ill)[0]
-        if cand.size:
-            ill[cand] = line_sensitive(o, st, cand, params)
-            rep["n_line_sensitive"] = int(ill[cand].sum())
+        # how far each agent outside the tolerance would move with its own
+        # half-planes rounded at FP32 size (eight draws)
+        mv = np.zeros(dv.shape)
+        idx = np.nonzero(bad)[0][:64]
+        if idx.size:
+            mv[idx] = line_movement(o, st, idx, params, reps=8)
+            rep["n_line_sensitive"] = int(np.sum(~ill[idx] & (mv[idx] > COND_TOL)))
+            ill[idx] |= mv[idx] > COND_TOL
         rep["n_ill"] = int(ill.sum())
         rep["n_bad_ill"] = int((bad & ill).sum())
         vmax = np.asarray(st["max_speed"], np.float64)
@@ -235,6 +251,13 @@ def compare_step(state_np, params, *, require_all=False, max_ill_frac=0.01, reps
         for a in np.nonzero(bad & ill & ~ok)[0][:32]:
             ok[a] = contact_flipped(st, params, a, g)
         rep["n_contact_flipped"] = rep["n_bad_ill_invalid"] - int((bad & ill & ~ok).sum())
+        # an ill-conditioned answer moves with rounding itself: an answer
+        # within twice the distance the oracle's own answer moves when its
+        # state (sens) or its own half-planes (mv) are perturbed at FP32 size
+        # is as close as FP32 can come
+        far = bad & ill & ~ok & (dv <= 2.0 * np.maximum(sens, mv))
+        ok |= far
+        rep["n_within_sensitivity"] = int(far.sum())
         # ill-conditioned agents must still hold a valid answer
         assert not (bad & ill & ~ok).any(), (rep, np.nonzero(bad & ill & ~ok)[0][:10])
     # every well-conditioned agent within tolerance

