@@ -50,6 +50,7 @@ extern "C" {
 #define ORCA_EWORKSPACE (-2) /* workspace smaller than orca_workspace_bytes() */
 #define ORCA_EHIP (-3)       /* a HIP launch reported an error */
 #define ORCA_ERANGE (-4)     /* max_neighbors outside 1..ORCA_K_MAX */
+#define ORCA_ETOOBIG (-5)    /* more agents than orca_step_noalloc's scratch holds */
 
 #define ORCA_K_MAX 32
 #define ORCA_N_MAX 268435456  /* agents per call (2^28) of the neighbour search */
@@ -304,6 +305,30 @@ size_t orca_overlap_workspace_bytes(int32_t n);
  * (also for n == 0).  reach > 0. */
 int orca_overlap_stats(const orca_agents_in *in, int32_t n, float reach, double *out, void *ws,
                        size_t ws_bytes, hipStream_t stream);
+
+/* ---- Stepping without a caller-provided workspace ------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).
+ *
+ * orca_step_noalloc is orca_step with the workspace replaced by a fixed
+ * scratch array inside the library, ORCA_NOALLOC_BYTES bytes of device
+ * memory per GPU, held from the first call on that GPU until the process
+ * ends.  It allocates and frees nothing.  The first call on a GPU looks the
+ * array up for that GPU and clears it with a fill kernel on `stream`; every
+ * call uses the array of the current device.
+ *  - n <= ORCA_NOALLOC_N_MAX, else ORCA_ETOOBIG (nothing is enqueued).
+ *  - Results equal orca_step's on a workspace of orca_workspace_bytes(n, 0,
+ *    0) bytes, bit for bit.
+ *  - Every call on one GPU shares that GPU's array, which keeps the last
+ *    call's contents (only the kept neighbour distances carry over, and they
+ *    never change a result).  Calls that overlap on one GPU -- on different
+ *    streams, or from different threads without ordering -- race on it and
+ *    give undefined results: serialise them on one stream. */
+#define ORCA_NOALLOC_N_MAX 262144
+#define ORCA_NOALLOC_BYTES (16u << 20)
+
+int orca_step_noalloc(const orca_agents_in *in, const orca_agents_out *out, int32_t n,
+                      const orca_params *params, hipStream_t stream);
 
 /* Human-readable text for a status code (static storage). */
 const char *orca_status_string(int code);

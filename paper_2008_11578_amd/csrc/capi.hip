@@ -5,6 +5,8 @@
 
 #include <math.h>
 
+#include <mutex>
+
 namespace orca {
 
 namespace {
@@ -188,6 +190,35 @@ int prepare(int32_t n, const orca_params *params, void *ws, size_t ws_bytes, Lay
     return ORCA_OK;
 }
 
+// Workspace of orca_step_noalloc: one array per GPU, in the library's own
+// device memory.  Host code never passes `scratch` itself to a kernel (on
+// the host that name is only a stand-in for the device array): it uses the
+// device address looked up once per device below.
+static __device__ __align__(256) unsigned char scratch[ORCA_NOALLOC_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// The current device's scratch address.  On the first call on a device:
+// hipGetSymbolAddress with that device current, then one fill kernel on
+// `stream` that clears the array before any use of it in stream order.
+int noalloc_scratch(hipStream_t stream, void **ptr)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return ORCA_EHIP;
+    if (dev < 0 || dev >= kMaxDevices) return ORCA_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return ORCA_EHIP;
+        if (launch_fill_zero(p, ORCA_NOALLOC_BYTES, stream) != hipSuccess) return ORCA_EHIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return ORCA_OK;
+}
+
 }  // namespace
 }  // namespace orca
 
@@ -276,6 +307,26 @@ int orca_step_nbr(const orca_agents_in *in, const orca_agents_out *out, int32_t 
                   int32_t *nbr_count, hipStream_t stream)
 {
     return step_impl(in, out, n, params, ws, ws_bytes, nullptr, nbr, nbr_count, stream);
+}
+
+int orca_step_noalloc(const orca_agents_in *in, const orca_agents_out *out, int32_t n,
+                      const orca_params *params, hipStream_t stream)
+{
+    // every argument is checked before the scratch set-up enqueues anything
+    if (n < 0) return ORCA_EINVAL;
+    if (n > ORCA_NOALLOC_N_MAX) return ORCA_ETOOBIG;
+    int rc = check_params(params);
+    if (rc != ORCA_OK || n == 0) return rc;
+    rc = check_in(in);
+    if (rc != ORCA_OK) return rc;
+    rc = check_out(out);
+    if (rc != ORCA_OK) return rc;
+    const size_t bytes = make_layout(n, 0, 0).total;
+    if (bytes > ORCA_NOALLOC_BYTES) return ORCA_ETOOBIG;
+    void *ws = nullptr;
+    rc = noalloc_scratch(stream, &ws);
+    if (rc != ORCA_OK) return rc;
+    return step_impl(in, out, n, params, ws, bytes, nullptr, nullptr, nullptr, stream);
 }
 
 int orca_step_batched(const orca_agents_in *in, const orca_agents_out *out, int32_t n,
@@ -433,6 +484,7 @@ const char *orca_status_string(int code)
     case ORCA_EWORKSPACE: return "workspace too small";
     case ORCA_EHIP: return "HIP launch error";
     case ORCA_ERANGE: return "max_neighbors outside 1..ORCA_K_MAX";
+    case ORCA_ETOOBIG: return "more agents than the no-allocation scratch holds";
     default: return "unknown status";
     }
 }

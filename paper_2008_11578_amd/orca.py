@@ -103,6 +103,9 @@ def lib() -> ctypes.CDLL:
         L.orca_step_nbr.argtypes = [ctypes.POINTER(AgentsIn), ctypes.POINTER(AgentsOut), i32,
                                     ctypes.POINTER(OrcaParams), vp, sz, vp, vp, vp]
         L.orca_step_batched.restype = ctypes.c_int
+        L.orca_step_noalloc.restype = ctypes.c_int
+        L.orca_step_noalloc.argtypes = [ctypes.POINTER(AgentsIn), ctypes.POINTER(AgentsOut), i32,
+                                        ctypes.POINTER(OrcaParams), vp]
         L.orca_step_batched.argtypes = [ctypes.POINTER(AgentsIn), ctypes.POINTER(AgentsOut), i32,
                                         ctypes.POINTER(OrcaBatch), vp, sz, vp]
         L.orca_step_batched_ex.restype = ctypes.c_int
@@ -319,6 +322,31 @@ def step_nbr(state: State, params, ws: Workspace, out: Optional[State] = None,
     if rc != ORCA_OK:
         raise OrcaError("orca_step_nbr", rc)
     return out, nbr, cnt
+
+
+NOALLOC_N_MAX = 262144
+
+
+def step_noalloc(state: State, params, out: Optional[State] = None,
+                 status: Optional[torch.Tensor] = None, stream=None) -> State:
+    """``orca_step_noalloc``: :func:`step` on the library's own per-GPU
+    scratch array instead of a workspace (at most ``NOALLOC_N_MAX`` agents;
+    calls on one GPU must not overlap)."""
+    p = make_params(params)
+    n = state.n
+    if out is None:
+        out = state.clone()
+    if status is not None:
+        _check(status, "status", torch.uint8, n)
+    for k in ("px", "py", "vx", "vy"):
+        _check(getattr(out, k), "out." + k, torch.float32, n)
+    ain = state.agents_in()
+    aout = AgentsOut(_ptr(out.px), _ptr(out.py), _ptr(out.vx), _ptr(out.vy), _ptr(status))
+    rc = lib().orca_step_noalloc(ctypes.byref(ain), ctypes.byref(aout), n, ctypes.byref(p),
+                                 _stream_handle(stream))
+    if rc != ORCA_OK:
+        raise OrcaError("orca_step_noalloc", rc)
+    return out
 
 
 def params_of(sc: "scenarios.Scenario"):

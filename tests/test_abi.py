@@ -227,3 +227,32 @@ def test_missing_library_fails_loudly(tmp_path):
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert r.returncode == 3, (r.stdout, r.stderr)
     assert "missing" in r.stdout
+
+
+def test_noalloc_argument_errors(orca_mod):
+    """orca_step_noalloc validates everything before it touches a device: n
+    above its scratch limit is ORCA_ETOOBIG, the rest as orca_step."""
+    lib = orca_mod.lib()
+    p = _params(orca_mod)
+    ain, aout = _in_fake(orca_mod), _out_fake(orca_mod)
+    n_max = orca_mod.NOALLOC_N_MAX
+    assert lib.orca_step_noalloc(ctypes.byref(ain), ctypes.byref(aout), n_max + 1,
+                                 ctypes.byref(p), None) == -5
+    assert lib.orca_step_noalloc(ctypes.byref(ain), ctypes.byref(aout), 1 << 28,
+                                 ctypes.byref(p), None) == -5
+    assert lib.orca_step_noalloc(None, None, 0, ctypes.byref(p), None) == 0
+    assert lib.orca_step_noalloc(ctypes.byref(ain), ctypes.byref(aout), -1, ctypes.byref(p),
+                                 None) == -1
+    assert lib.orca_step_noalloc(ctypes.byref(ain), ctypes.byref(aout), 10, None, None) == -1
+    bad = _params(orca_mod, max_neighbors=33)
+    assert lib.orca_step_noalloc(ctypes.byref(ain), ctypes.byref(aout), 10, ctypes.byref(bad),
+                                 None) == -4
+    bad_in = orca_mod.AgentsIn(*([FAKE] * 8 + [None]))
+    assert lib.orca_step_noalloc(ctypes.byref(bad_in), ctypes.byref(aout), 10, ctypes.byref(p),
+                                 None) == -1
+    bad_out = orca_mod.AgentsOut(FAKE, None, FAKE, FAKE, None)
+    assert lib.orca_step_noalloc(ctypes.byref(ain), ctypes.byref(bad_out), 10, ctypes.byref(p),
+                                 None) == -1
+    assert "no-allocation" in orca_mod.status_string(-5)
+    # the largest accepted crowd fits the scratch array
+    assert orca_mod.workspace_bytes(n_max) <= 16 << 20
