@@ -192,46 +192,6 @@ struct NoGroupEnd {
     __device__ __forceinline__ void operator()() const {}
 };
 
-// Visits the cell-order candidates [ra, rb) (ra < rb) in groups of
-// kScanUnroll as visit(c, t, valid) (c = s0[t]), calling group_end() after
-// each group.  A group always loads all its members (the last one reads up
-// to kScanUnroll - 1 entries past rb, inside s0 and its padding) and passes
-// valid = t < rb, so the visitor runs without a remainder loop and can stay
-// branch-free.  The next group is loaded before the current one is visited.
-template <class F, class G = NoGroupEnd>
-__device__ __forceinline__ void scan_range(const float4 *__restrict__ s0, uint32_t ra, uint32_t rb,
-                                           F &&visit, G &&group_end = G())
-{
-    // two register groups used in turn, so no group is copied; components a
-    // visitor does not read are never loaded
-    float4 c[kScanUnroll], d[kScanUnroll];
-    const float4 *p = s0 + ra;
-#pragma unroll
-    for (int q = 0; q < kScanUnroll; ++q) c[q] = p[q];
-    for (uint32_t t = ra;; t += 2 * kScanUnroll) {
-        const bool more1 = t + kScanUnroll < rb;
-        if (more1) {
-#pragma unroll
-            for (int q = 0; q < kScanUnroll; ++q) d[q] = p[kScanUnroll + q];
-        }
-#pragma unroll
-        for (int q = 0; q < kScanUnroll; ++q) visit(c[q], t + q, t + q < rb);
-        group_end();
-        if (!more1) break;
-        const bool more2 = t + 2 * kScanUnroll < rb;
-        if (more2) {
-#pragma unroll
-            for (int q = 0; q < kScanUnroll; ++q) c[q] = p[2 * kScanUnroll + q];
-        }
-        const uint32_t u = t + kScanUnroll;
-#pragma unroll
-        for (int q = 0; q < kScanUnroll; ++q) visit(d[q], u + q, u + q < rb);
-        group_end();
-        if (!more2) break;
-        p += 2 * kScanUnroll;
-    }
-}
-
 // Grid rows that can hold an agent within sqrt(r2) of y (r2 <= R_n^2).
 __device__ __forceinline__ void row_span(const GridMeta &g, double yd, double r2, int &ya, int &yb)
 {
@@ -242,24 +202,37 @@ __device__ __forceinline__ void row_span(const GridMeta &g, double yd, double r2
     yb = (int)fmin(fmax(ub, 0.0), (double)(g.ny - 1));
 }
 
-// Cell-order range of row yy clipped to the chord of the circle of squared
-// radius r2 around (xd, yd); false when empty.
-__device__ __forceinline__ bool row_range(const GridMeta &g, const uint32_t *__restrict__ start,
-                                          double xd, double yd, double r2, int yy, uint32_t &a,
-                                          uint32_t &b)
+// Cell indices [xa, xb] of row yy's cells that meet the chord of the circle
+// of squared radius r2 around (xd, yd) (FP64, with 1e-6-cell margins);
+// false when the chord misses the row (xa = xb = the column of xd then).
+// Returns the offsets of the two `start` entries that bound the row's range.
+__device__ __forceinline__ bool row_cells(const GridMeta &g, double xd, double yd, double r2, int yy,
+                                          int &ia, int &ib)
 {
     const double ylo = (double)g.y0 + (double)yy * g.cs_d;
     const double dy = fmax(fmax(ylo - yd, yd - (ylo + g.cs_d)) - 1e-6 * g.cs_d, 0.0);
     const double h2 = r2 - dy * dy;
-    if (!(h2 > 0.0)) return false;
-    const double hw = sqrt(h2);
+    const bool meets = h2 > 0.0;
+    const double hw = meets ? sqrt(h2) : 0.0;
     const double ua = floor((xd - hw - (double)g.x0) * g.inv_cs - 1e-6);
     const double ub = floor((xd + hw - (double)g.x0) * g.inv_cs + 1e-6);
     const int xa = (int)fmin(fmax(ua, 0.0), (double)(g.nx - 1));
     const int xb = (int)fmin(fmax(ub, 0.0), (double)(g.nx - 1));
     const int row = g.cell_base + yy * g.nx;
-    a = start[row + xa];
-    b = start[row + xb + 1];
+    ia = row + xa;
+    ib = row + xb + 1;
+    return meets;
+}
+
+// Cell-order range of row yy clipped to the chord; false when empty.
+__device__ __forceinline__ bool row_range(const GridMeta &g, const uint32_t *__restrict__ start,
+                                          double xd, double yd, double r2, int yy, uint32_t &a,
+                                          uint32_t &b)
+{
+    int ia, ib;
+    if (!row_cells(g, xd, yd, r2, yy, ia, ib)) return false;
+    a = start[ia];
+    b = start[ib];
     if (b > g.seg_end) b = g.seg_end;  // defensive: stay inside the scene
     return a < b;
 }
@@ -303,23 +276,105 @@ __device__ __forceinline__ void sort_network(uint32_t (&e)[N])
 }
 
 // Visits every candidate in the grid rows and chords of the circle of
-// squared radius r2 around (xd, yd), row by row; the next row's range (two
-// loads from `start`) is requested before the current row is scanned.
+// squared radius r2 around (xd, yd), row by row and in cell order within a
+// row, in groups of kScanUnroll as visit(c, t, valid) (c = s0[t]), calling
+// group_end() after each group.  A group always loads all its members (the
+// last one of a row reads up to kScanUnroll - 1 entries past the row's end,
+// inside s0 and its padding) and passes valid = t < end of its row, so the
+// visitor runs without a remainder loop and can stay branch-free.
+//
+// The loop runs over groups, not rows, with the memory one step ahead of
+// the arithmetic: the next group -- the next one of the same row or the
+// first one of the next row -- is loaded before the current one is visited,
+// and a row's range is loaded from `start` one group before it is entered.
+// Every lane issues both loads on every pass (a lane that stays in its row
+// loads the same entries again), so the number of loads in flight is the
+// same on every path and each wait covers only the data it needs.  In a
+// dense crowd a row chord holds fewer candidates than one group, so a loop
+// per row would wait for the memory at every row.  A row whose range turns
+// out empty costs one group of invalid members.  Lanes step through their
+// own rows, so a wave runs as many groups as its busiest lane.
 template <class F, class G = NoGroupEnd>
 __device__ __forceinline__ void scan_disc(const GridMeta &g, const uint32_t *__restrict__ start,
                                           const float4 *__restrict__ s0, double xd, double yd,
                                           double r2, F &&visit, G &&group_end = G())
 {
-    int ya, yb;
-    row_span(g, yd, r2, ya, yb);
-    uint32_t na = 0, nb = 0;
-    bool nok = row_range(g, start, xd, yd, r2, ya, na, nb);
-    for (int yy = ya; yy <= yb; ++yy) {
-        const uint32_t ra = na, rb = nb;
-        const bool ok = nok;
-        if (yy < yb) nok = row_range(g, start, xd, yd, r2, yy + 1, na, nb);
-        if (ok) scan_range(s0, ra, rb, visit, group_end);
+    int yr, yb;
+    row_span(g, yd, r2, yr, yb);
+    // The range of row yr is loaded into one of two register pairs while the
+    // other pair, loaded a pass earlier, is consumed (the two swap roles every
+    // pass, so a load never lands in a register that is still being read);
+    // rm: row yr's chord meets the row; (ia, ib): its `start` offsets.
+    int ia, ib;
+    bool rm = row_cells(g, xd, yd, r2, yr, ia, ib);
+    uint32_t pa[2], pb[2];
+    pa[0] = start[ia];
+    pb[0] = start[ib];
+    // the group after [t, t + kScanUnroll) of row [.., e): the next one of
+    // the row, else the first one of row yr, whose range (pair P) is then
+    // consumed and row yr + 1 requested; pair 1 - P is (re)loaded with the
+    // range of the row requested now; false when no row is left
+    auto next_group = [&](int P, uint32_t t, uint32_t e, uint32_t &tn, uint32_t &en) -> bool {
+        const bool stay = t + kScanUnroll < e;
+        bool live = true;
+        if (stay) {
+            tn = t + kScanUnroll;
+            en = e;
+        } else {
+            live = yr <= yb;
+            tn = pa[P];
+            en = pb[P] < g.seg_end ? pb[P] : g.seg_end;  // defensive: stay inside the scene
+            if (!rm || !(tn < en)) en = tn;              // an empty row: no valid member
+            ++yr;
+            if (yr <= yb) rm = row_cells(g, xd, yd, r2, yr, ia, ib);
+        }
+        pa[1 - P] = start[ia];
+        pb[1 - P] = start[ib];
+        return live;
+    };
+    // two register groups used in turn, so no group is copied; components a
+    // visitor does not read are never loaded
+    float4 c[kScanUnroll], d[kScanUnroll];
+    uint32_t t0 = 0, e0 = 0;
+    next_group(0, 0u, 0u, t0, e0);  // row yr exists: yr <= yb here
+    {
+        const float4 *pc = s0 + t0;
+#pragma unroll
+        for (int q = 0; q < kScanUnroll; ++q) c[q] = pc[q];
     }
+    for (;;) {
+        uint32_t t1, e1;
+        const bool more1 = next_group(1, t0, e0, t1, e1);
+        {
+            const float4 *pd = s0 + (more1 ? t1 : t0);
+#pragma unroll
+            for (int q = 0; q < kScanUnroll; ++q) d[q] = pd[q];
+        }
+        // keep the loads ahead of the visit (the scheduler would otherwise
+        // move them next to their use)
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < kScanUnroll; ++q) visit(c[q], t0 + q, t0 + q < e0);
+        group_end();
+        if (!more1) break;
+        const bool more2 = next_group(0, t1, e1, t0, e0);
+        {
+            const float4 *pc = s0 + (more2 ? t0 : t1);
+#pragma unroll
+            for (int q = 0; q < kScanUnroll; ++q) c[q] = pc[q];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < kScanUnroll; ++q) visit(d[q], t1 + q, t1 + q < e1);
+        group_end();
+        if (!more2) break;
+    }
+    // the loads of the last pass are read on the way out too, so that the
+    // compiler keeps each prefetch where it is written instead of moving it
+    // behind the exit test, next to its use
+#pragma unroll
+    for (int q = 0; q < kScanUnroll; ++q)
+        asm volatile("" ::"v"(c[q].x), "v"(c[q].y), "v"(d[q].x), "v"(d[q].y));
 }
 
 // Selects the (at most K) nearest agents of the lane into entries [0, m) of
