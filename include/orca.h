@@ -101,6 +101,18 @@ typedef struct {
                              taken.)  orca_step_backward differentiates the
                              octagon through its centre (a and dt are
                              constants). */
+    float turn[2];        /* turn-rate cap per class [rad/s], >= 0; 0 = none.
+                             The non-holonomic half of the same Sec. 5
+                             extension: a vehicle moves along its heading (the
+                             direction of its current velocity) and turns it by
+                             at most turn*dt per step, so the new velocity must
+                             lie in the wedge of half-angle
+                             phi = min(turn*dt, pi/2) about the heading, apex
+                             at the origin.  The wedge's two sides are hard
+                             lines after the acceleration lines.  An agent at
+                             rest has no heading and no wedge.
+                             orca_step_backward rejects turn > 0 (ORCA_EINVAL):
+                             the wedge is not differentiated. */
 } orca_params;
 
 /* Bytes of workspace needed for n agents (plain step / grid), or for a
@@ -174,12 +186,13 @@ typedef struct {
                                      (default); 1: one workgroup per tile */
     int32_t *error_flag;          /* DEVICE, nullable: set to 1 (never cleared) when
                                      an offset or a scene's parameters are invalid
-                                     (including an accel cap > 0 while has_accel
-                                     is 0); the kernels clamp every index
-                                     regardless */
-    int32_t has_accel;            /* HOST: 1 if any scene has accel[c] > 0 (selects
-                                     the kernel with acceleration lines; without it
-                                     caps are ignored and flagged), else 0 */
+                                     (including an accel or turn cap > 0 while
+                                     has_accel is 0); the kernels clamp every
+                                     index regardless */
+    int32_t has_accel;            /* HOST: 1 if any scene has accel[c] > 0 or
+                                     turn[c] > 0 (selects the kernel with hard
+                                     lines; without it caps are ignored and
+                                     flagged), else 0 */
     int32_t block;                /* HOST: lanes per workgroup of the step kernel,
                                      64, 128 or 256 (1, 2 or 4 wavefronts); 0 = 128 */
     int32_t k_tile;               /* HOST: neighbour-list capacity compiled into the

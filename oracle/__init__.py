@@ -42,7 +42,7 @@ class _OParams(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("tau", ctypes.c_double), ("rn", ctypes.c_double),
                 ("k", ctypes.c_int32), ("pref_is_goal", ctypes.c_int32),
                 ("f", (ctypes.c_double * 2) * 2), ("eps", ctypes.c_double),
-                ("accel", ctypes.c_double * 2)]
+                ("accel", ctypes.c_double * 2), ("turn", ctypes.c_double * 2)]
 
 
 _lib = None
@@ -88,6 +88,8 @@ def lib():
             [ctypes.c_double] * 6 + [dp]
         L.oracle_accel_lines.restype = ctypes.c_int
         L.oracle_accel_lines.argtypes = [ctypes.c_double] * 5 + [dp]
+        L.oracle_turn_lines.restype = ctypes.c_int
+        L.oracle_turn_lines.argtypes = [ctypes.c_double] * 4 + [dp]
         L.oracle_set_threads.restype = ctypes.c_int
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         L.oracle_step_batched.restype = ctypes.c_int
@@ -220,6 +222,13 @@ def make_params(params) -> _OParams:
     acc = (0.0, 0.0) if acc is None else acc
     for c in range(2):
         p.accel[c] = _f32d(acc[c])
+    try:
+        turn = g("turn")
+    except (AttributeError, KeyError):
+        turn = None
+    turn = (0.0, 0.0) if turn is None else turn
+    for c in range(2):
+        p.turn[c] = _f32d(turn[c])
     return p
 
 
@@ -263,8 +272,8 @@ def lp_full(lines, vmax, opt, eps=1e-5):
 
 
 def lp_full_hard(lines, n_hard, vmax, opt, centre, eps=1e-5):
-    """LP2/LP3 with the first `n_hard` lines never relaxed (acceleration
-    lines); a failure among them takes v = centre.  Returns (v, fail)."""
+    """LP2/LP3 with the first `n_hard` lines never relaxed (acceleration and
+    heading lines); a failure among them takes v = centre.  Returns (v, fail)."""
     lines = np.ascontiguousarray(lines, dtype=np.float64).reshape(-1, 4)
     v = (ctypes.c_double * 2)()
     fail = lib().oracle_lp_full_hard(lines.shape[0], int(n_hard),
@@ -283,6 +292,15 @@ def accel_lines(v, vmax, accel, dt):
     m = lib().oracle_accel_lines(float(v[0]), float(v[1]), float(vmax), float(accel), float(dt),
                                  out)
     return np.array(out[:]).reshape(8, 4)[:m]
+
+
+def turn_lines(v, turn, dt):
+    """The heading lines (2 x 4, or 0 x 4 when turn <= 0 or v = 0) of an
+    agent with current velocity v: the sides of the wedge of half-angle
+    min(turn dt, pi/2) about its heading, through the origin."""
+    out = (ctypes.c_double * 8)()
+    m = lib().oracle_turn_lines(float(v[0]), float(v[1]), float(turn), float(dt), out)
+    return np.array(out[:]).reshape(2, 4)[:m]
 
 
 def knn(px, py, neighbor_dist, k):

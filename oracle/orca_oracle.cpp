@@ -35,8 +35,9 @@
  *    largest penetration.
  *  - desired velocity and update: Sec. 3 / Sec. 4 (velocity toward the goal
  *    scaled to the speed; all agents updated simultaneously, explicit Euler).
- *  - acceleration limit: Sec. 5 (vehicles whose own motion limits add
- *    linear constraints to the same LP); see accel_lines.
+ *  - acceleration and turn-rate limits: Sec. 5 (vehicles whose own motion
+ *    limits -- acceleration, non-holonomic motion -- add linear constraints
+ *    to the same LP); see accel_lines and turn_lines.
  *
  * Gradient (not in the paper; the differentiable form of the step): every
  * function of one agent's update is a template over its scalar type.  With
@@ -61,7 +62,9 @@
 #include <omp.h>
 
 #define ORACLE_K_MAX 64
-#define ORACLE_HARD 8 /* acceleration lines of an acceleration-limited agent */
+#define ORACLE_ACC 8   /* acceleration lines of an acceleration-limited agent */
+#define ORACLE_TURN 2  /* heading lines of a turn-rate-limited agent */
+#define ORACLE_HARD (ORACLE_ACC + ORACLE_TURN)
 #define ORACLE_NWORK 12
 
 namespace {
@@ -155,6 +158,7 @@ struct OParams {
     double f[2][2];
     double eps;
     double accel[2]; /* acceleration cap per class [m/s^2]; 0 = none */
+    double turn[2];  /* turn-rate cap per class [rad/s]; 0 = none */
 };
 
 /* ------------------------------------------------------------------------ */
@@ -284,7 +288,10 @@ int lp1(const Line<T> *L, int i, double vmax, T ox, T oy, int mode, T tx, T ty, 
         const T a = det2(lj->dx, lj->dy, li->dx, li->dy);
         const T b = det2(lj->dx, lj->dy, li->qx - lj->qx, li->qy - lj->qy);
         if (fabs(val(a)) <= eps) {
-            if (val(b) < 0.0) {
+            /* parallel within eps: line i lies wholly outside line j only
+             * when it is offset to j's forbidden side by more than
+             * 2^-20 v_max; closer than that the two are the same line */
+            if (val(b) < -std::ldexp(vmax, -20)) {
                 tr.mix(21);
                 return 0;
             }
@@ -503,14 +510,48 @@ int accel_lines(T vx, T vy, double vmax, double accel, double dt, Line<T> *out)
     T cx, cy;
     accel_centre<T>(vx, vy, vmax, &cx, &cy);
     const double h = accel * dt * std::cos(M_PI / 8.0);
-    for (int k = 0; k < ORACLE_HARD; ++k) {
+    for (int k = 0; k < ORACLE_ACC; ++k) {
         const double nx = std::cos(k * M_PI / 4.0), ny = std::sin(k * M_PI / 4.0);
         out[k].qx = cx + h * nx;
         out[k].qy = cy + h * ny;
         out[k].dx = T(-ny);
         out[k].dy = T(nx);
     }
-    return ORACLE_HARD;
+    return ORACLE_ACC;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Turn-rate limit: the non-holonomic half of the same Sec. 5 extension.    */
+/* Reading: a vehicle moves along its heading, the direction of its current */
+/* velocity, and can turn it by at most w dt within one step, so the new    */
+/* velocity must lie in the wedge of half-angle phi = min(w dt, pi/2) about */
+/* that heading, apex at the origin (braking to rest stays possible).  For  */
+/* phi <= pi/2 the wedge is convex: with h = v/|v| and R(a) the rotation by */
+/* a, its sides are the rays along r_R = R(-phi) h and r_L = R(phi) h, and  */
+/* the constraints det(r_R, v) >= 0, det(v, r_L) >= 0 are the lines through */
+/* the origin with directions r_R and -r_L (permitted side on the left).    */
+/* At rest (v = 0) there is no heading and no wedge.  The lines are hard,   */
+/* after any acceleration lines.  Returns the number written (0 or 2).      */
+/* ------------------------------------------------------------------------ */
+template <class T>
+int turn_lines(T vx, T vy, double turn, double dt, Line<T> *out)
+{
+    if (!(turn > 0.0)) return 0;
+    const T v2 = vx * vx + vy * vy;
+    if (!(val(v2) > 0.0)) return 0;
+    const T sp = sqrt_(v2);
+    const T hx = vx / sp, hy = vy / sp;
+    const double phi = std::min(turn * dt, M_PI / 2.0);
+    const double c = std::cos(phi), s = std::sin(phi);
+    out[0].qx = T(0.0);
+    out[0].qy = T(0.0);
+    out[0].dx = hx * c + hy * s; /* r_R */
+    out[0].dy = hy * c - hx * s;
+    out[1].qx = T(0.0);
+    out[1].qy = T(0.0);
+    out[1].dx = -(hx * c - hy * s); /* -r_L */
+    out[1].dy = -(hy * c + hx * s);
+    return ORACLE_TURN;
 }
 
 template <class T>
@@ -519,7 +560,8 @@ int agent_update(const AgentIn<T> &a, int self, double r, int cls, double vmax, 
                  T *vx_out, T *vy_out, int64_t *w, Trace &tr)
 {
     Line<T> L[ORACLE_K_MAX + ORACLE_HARD];
-    const int nh = accel_lines<T>(a.vx, a.vy, vmax, prm.accel[cls & 1], prm.dt, L);
+    const int na = accel_lines<T>(a.vx, a.vy, vmax, prm.accel[cls & 1], prm.dt, L);
+    const int nh = na + turn_lines<T>(a.vx, a.vy, prm.turn[cls & 1], prm.dt, L + na);
     if (nh) tr.mix(val(a.vx * a.vx + a.vy * a.vy) > vmax * vmax ? 71 : 70); /* centre clipped */
     T prx, pry;
     if (prm.pref_is_goal) {
@@ -555,8 +597,9 @@ int agent_update(const AgentIn<T> &a, int self, double r, int cls, double vmax, 
                            &w[4], &w[5], tr);
     int st = 0;
     if (fail < nh) {
-        /* the hard lines and the speed disc always meet (the centre of the
-         * octagon lies in the disc), so this is rounding alone; the centre
+        /* the hard lines and the speed disc always meet (the centre, the
+         * current velocity scaled into the disc, lies in the octagon and on
+         * the heading wedge's axis), so this is rounding alone; the centre
          * itself is then taken and LP3 starts from it */
         accel_centre<T>(a.vx, a.vy, vmax, &nvx, &nvy);
         tr.mix(60);
@@ -710,7 +753,9 @@ bool params_ok(const OParams *prm)
 {
     return prm && prm->k >= 1 && prm->k <= ORACLE_K_MAX && prm->dt > 0.0 && prm->tau > 0.0 &&
            prm->rn > 0.0 && prm->accel[0] >= 0.0 && prm->accel[1] >= 0.0 &&
-           std::isfinite(prm->accel[0]) && std::isfinite(prm->accel[1]);
+           std::isfinite(prm->accel[0]) && std::isfinite(prm->accel[1]) &&
+           prm->turn[0] >= 0.0 && prm->turn[1] >= 0.0 && std::isfinite(prm->turn[0]) &&
+           std::isfinite(prm->turn[1]);
 }
 
 /* One synchronous step of every agent of one scene (double state). */
@@ -1003,8 +1048,24 @@ int oracle_lp_full_hard(int m, int nh, const double *lines, double vmax, double 
  * dy); returns the count (0 when accel <= 0). */
 int oracle_accel_lines(double vx, double vy, double vmax, double accel, double dt, double *out)
 {
-    Line<double> L[ORACLE_HARD];
+    Line<double> L[ORACLE_ACC];
     const int nh = accel_lines<double>(vx, vy, vmax, accel, dt, L);
+    for (int k = 0; k < nh; ++k) {
+        out[4 * k + 0] = L[k].qx;
+        out[4 * k + 1] = L[k].qy;
+        out[4 * k + 2] = L[k].dx;
+        out[4 * k + 3] = L[k].dy;
+    }
+    return nh;
+}
+
+/* The two heading lines of a turn-rate-limited agent with current velocity
+ * (vx, vy), cap turn [rad/s] and step dt, as 2 x 4 (qx, qy, dx, dy);
+ * returns the count (0 when turn <= 0 or v = 0). */
+int oracle_turn_lines(double vx, double vy, double turn, double dt, double *out)
+{
+    Line<double> L[ORACLE_TURN];
+    const int nh = turn_lines<double>(vx, vy, turn, dt, L);
     for (int k = 0; k < nh; ++k) {
         out[4 * k + 0] = L[k].qx;
         out[4 * k + 1] = L[k].qy;

@@ -192,7 +192,7 @@ __device__ __forceinline__ void adjoint_agent(int s, const AdjArgs &a, const Gri
         pos[q] = q < m ? dev::entry_pos(buf[dev::buf_idx<BLOCK>(q, tid)]) : 0u;
     const float vmax = a.in.max_speed[i];
     const float acc = ACC ? (ci ? p.acc1 : p.acc0) : 0.0f;
-    const int nh = (ACC && acc > 0.0f) ? dev::kHard : 0;
+    const int nh = (ACC && acc > 0.0f) ? dev::kAccLines : 0;
     dev::build_halfplanes<K, BLOCK>(pos, m, a.s0, a.s1, xi, yi, vxi, vyi, ri, i, ci, p, lines,
                                     tid);
     float cx = 0.0f, cy = 0.0f;

@@ -80,7 +80,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_bbox(const float *__restrict__
                   (p.pref_is_goal != 0 && p.pref_is_goal != 1) ||
                   !(p.accel[0] >= 0.0f) || !(p.accel[1] >= 0.0f) ||
                   !isfinite(p.accel[0]) || !isfinite(p.accel[1]) ||
-                  (!has_accel && (p.accel[0] > 0.0f || p.accel[1] > 0.0f));
+                  !(p.turn[0] >= 0.0f) || !(p.turn[1] >= 0.0f) ||
+                  !isfinite(p.turn[0]) || !isfinite(p.turn[1]) ||
+                  (!has_accel && (p.accel[0] > 0.0f || p.accel[1] > 0.0f ||
+                                  p.turn[0] > 0.0f || p.turn[1] > 0.0f));
             if (bad) atomicOr(error_flag, 1);
         }
     }

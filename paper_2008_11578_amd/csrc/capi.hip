@@ -143,6 +143,8 @@ int check_params(const orca_params *p)
     if (p->pref_is_goal != 0 && p->pref_is_goal != 1) return ORCA_EINVAL;
     for (int c = 0; c < 2; ++c)
         if (!(p->accel[c] >= 0.0f) || !isfinite(p->accel[c])) return ORCA_EINVAL;
+    for (int c = 0; c < 2; ++c)
+        if (!(p->turn[c] >= 0.0f) || !isfinite(p->turn[c])) return ORCA_EINVAL;
     return ORCA_OK;
 }
 
@@ -386,6 +388,8 @@ int orca_step_backward_ex(const orca_agents_in *in, int32_t n, const orca_params
     if (n < 0 || n > ORCA_N_MAX) return ORCA_EINVAL;
     int rc = check_params(params);
     if (rc != ORCA_OK) return rc;
+    // the heading wedge is not differentiated
+    if (params->turn[0] > 0.0f || params->turn[1] > 0.0f) return ORCA_EINVAL;
     if (n == 0) return ORCA_OK;
     rc = check_in(in);
     if (rc != ORCA_OK) return rc;

@@ -119,8 +119,10 @@ struct KnnShape {
 #endif
 constexpr double kGuessSpeedSteps = ORCA_GUESS_SPEED_STEPS;
 
-// Acceleration lines of an acceleration-limited agent (see accel_line).
-constexpr int kHard = 8;
+// Hard lines of a vehicle's own motion limits: the acceleration octagon (see
+// accel_line) and the two sides of the heading wedge (see turn_wedge).
+constexpr int kAccLines = 8;
+constexpr int kTurnLines = 2;
 
 // Entry e of lane `tid` inside a [slot][BLOCK] float4 array viewed as u64.
 // With several wavefronts per block, both entries of a 16-byte slot stay in
@@ -694,15 +696,44 @@ __device__ __forceinline__ float4 accel_line(int k, float cx, float cy, float h)
     return make_float4(fmaf(h, nx, cx), fmaf(h, ny, cy), -ny, nx);
 }
 
-// The lines of this lane's LP: with ACC the first nh are its acceleration
-// lines (generated from the centre (cx, cy) and half-width h), then the
-// half-planes, stored in LDS column `tid`.
+// Turn-rate limit (the non-holonomic half of the same Sec. 5 extension): a
+// vehicle moves along its heading, the direction of its current velocity,
+// and turns it by at most w dt per step, so the new velocity lies in the
+// wedge of half-angle phi = min(w dt, pi/2) about the heading, apex at the
+// origin.  Its sides are the lines through the origin with directions
+// r_R = R(-phi) h and -r_L = -R(phi) h (permitted side on the left), hard
+// constraints after any acceleration lines.  Returns false at rest (no
+// heading, no wedge).  The heading is formed in double, so that a speed
+// whose square underflows FP32 still has one.
+__device__ __forceinline__ bool turn_wedge(float vx, float vy, float turn, float dt, float &rx,
+                                           float &ry, float &lx, float &ly)
+{
+    const double v2 = (double)vx * vx + (double)vy * vy;
+    if (!(turn > 0.0f) || !(v2 > 0.0)) return false;
+    const double inv = 1.0 / sqrt(v2);
+    const float hx = (float)(vx * inv), hy = (float)(vy * inv);
+    const float phi = fminf(turn * dt, 1.57079633f);
+    float sn, cs;
+    sincosf(phi, &sn, &cs);
+    rx = hx * cs + hy * sn;
+    ry = hy * cs - hx * sn;
+    lx = -(hx * cs - hy * sn);
+    ly = -(hy * cs + hx * sn);
+    return true;
+}
+
+// The lines of this lane's LP: with ACC the first nh are hard -- nacc
+// acceleration lines (generated from the centre (cx, cy) and half-width h),
+// then the wedge sides (through the origin, directions (rx, ry), (lx, ly))
+// -- followed by the half-planes, stored in LDS column `tid`.
 template <int BLOCK, bool ACC = false>
 struct LdsLines {
     const float4 *L;
     int tid;
     int nh = 0;
     float cx = 0.0f, cy = 0.0f, h = 0.0f;
+    int nacc = kAccLines;
+    float rx = 0.0f, ry = 0.0f, lx = 0.0f, ly = 0.0f;
     __device__ __forceinline__ float4 line(int j) const
     {
         if (!ACC) return L[j * BLOCK + tid];
@@ -711,9 +742,11 @@ struct LdsLines {
         // agent without a cap gets the same bits from both kernels
         const float4 s = L[(j >= nh ? j - nh : 0) * BLOCK + tid];
         const float4 a = accel_line(j, cx, cy, h);
-        const bool hard = j < nh;
-        return make_float4(hard ? a.x : s.x, hard ? a.y : s.y, hard ? a.z : s.z,
-                           hard ? a.w : s.w);
+        const bool right = j == nacc;
+        const float wx = right ? rx : lx, wy = right ? ry : ly;
+        const bool hard = j < nh, oct = j < nacc;
+        return make_float4(hard ? (oct ? a.x : 0.0f) : s.x, hard ? (oct ? a.y : 0.0f) : s.y,
+                           hard ? (oct ? a.z : wx) : s.z, hard ? (oct ? a.w : wy) : s.w);
     }
     __device__ __forceinline__ bool get(int j, float4 &l) const
     {
@@ -834,7 +867,7 @@ struct ActiveSet {
 };
 
 // What the LP's scalar type resolves in a velocity, relative to v_max (about
-// 16 ulps): the slack of lp1's feasibility test and the least excess over
+// 16 ulps): the slack of lp1's interval test and the least excess over
 // LP3's level that makes a line be re-solved.
 template <class S>
 struct FeasSlack;
@@ -889,6 +922,11 @@ __device__ __forceinline__ bool lp1(const Src &src, int i, typename LpVec<S>::T 
     // empty or not by rounding alone, and the point found then violates a
     // constraint by no more than that.
     const S slack = vmax * FeasSlack<S>::v;
+    // Lines parallel within eps are one line when line i is offset to j's
+    // forbidden side by no more than 2^-20 v_max (far below what the FP32
+    // positions resolve), else disjoint; the same offset in either precision
+    // and in the FP64 reference.
+    const S pslack = vmax * (S)0x1p-20;
     bool ok = true;
     for (int j = 0; j < i; ++j) {
         V4 lj;
@@ -904,7 +942,7 @@ __device__ __forceinline__ bool lp1(const Src &src, int i, typename LpVec<S>::T 
         sl = lo ? j : sl;
         tr = hi ? t : tr;
         sr = hi ? j : sr;
-        ok = ok && !(valid && par && b < -slack) && !(tl > tr + slack);
+        ok = ok && !(valid && par && b < -pslack) && !(tl > tr + slack);
     }
     if (!ok) return false;
     S t;
@@ -1047,7 +1085,8 @@ struct SceneP {
     int k;
     int pref_is_goal;
     float f00, f01, f10, f11;
-    float acc0, acc1;  // acceleration cap per class (0: none)
+    float acc0, acc1;    // acceleration cap per class (0: none)
+    float turn0, turn1;  // turn-rate cap per class (0: none)
 };
 
 __device__ __host__ __forceinline__ SceneP scene_params(const orca_params &p)
@@ -1065,6 +1104,8 @@ __device__ __host__ __forceinline__ SceneP scene_params(const orca_params &p)
     s.f11 = p.f[1][1];
     s.acc0 = p.accel[0];
     s.acc1 = p.accel[1];
+    s.turn0 = p.turn[0];
+    s.turn1 = p.turn[1];
     return s;
 }
 
@@ -1179,21 +1220,27 @@ __device__ __forceinline__ void step_agent(int s, const GridMeta &g, const Scene
 
     float prx = in.pref_x[i], pry = in.pref_y[i];
     const float acc = ACC ? (ci ? p.acc1 : p.acc0) : 0.0f;
-    const int nh = (ACC && acc > 0.0f) ? kHard : 0;
+    const float turn = ACC ? (ci ? p.turn1 : p.turn0) : 0.0f;
+    const int nacc = (ACC && acc > 0.0f) ? kAccLines : 0;
+    float rx = 0.0f, ry = 0.0f, lx = 0.0f, ly = 0.0f;
+    const int nh = nacc + ((ACC && turn_wedge(vxi, vyi, turn, p.dt, rx, ry, lx, ly))
+                               ? kTurnLines : 0);
     build_halfplanes<K, BLOCK>(pos, m, s0, s1, xi, yi, vxi, vyi, ri, i, ci, p, lines, tid);
     float cx = 0.0f, cy = 0.0f;
     if (ACC && nh) accel_centre(vxi, vyi, vmax, cx, cy);
     desired_velocity(p, xi, yi, vmax, prx, pry);
 
     const LdsLines<BLOCK, ACC> src{lines, tid, nh, cx, cy,
-                                   ACC && nh ? accel_half_width(acc, p.dt) : 0.0f};
+                                   ACC && nacc ? accel_half_width(acc, p.dt) : 0.0f,
+                                   nacc, rx, ry, lx, ly};
     const int mt = nh + m;
     float vx, vy;
     int fail = lp2<false, float>(src, mt, vmax, 0, prx, pry, 0.0f, 0.0f, p.eps, vx, vy, nullptr);
     uint8_t st = 0;
     if (ACC && fail < nh) {
-        // the octagon's centre lies in the speed disc, so only rounding can
-        // get here: take the centre and let LP3 start from it
+        // the centre (the current velocity scaled into the speed disc) lies
+        // in the octagon and on the wedge's axis, so only rounding can get
+        // here: take the centre and let LP3 start from it
         vx = cx;
         vy = cy;
         fail = nh;

@@ -90,9 +90,10 @@ template <int K>
 void launch_step_k(const StepArgs &a, hipStream_t stream)
 {
     const int nb = (a.n + kStepBlock - 1) / kStepBlock;
-    // the variant with acceleration lines only when a class has a cap, the
-    // exporting variant only when lists are asked for
-    const bool acc = a.prm.accel[0] > 0.0f || a.prm.accel[1] > 0.0f;
+    // the variant with hard lines (acceleration, heading) only when a class
+    // has a cap, the exporting variant only when lists are asked for
+    const bool acc = a.prm.accel[0] > 0.0f || a.prm.accel[1] > 0.0f || a.prm.turn[0] > 0.0f ||
+                     a.prm.turn[1] > 0.0f;
     const bool exp = a.nbr || a.cnt;
     const dev::SceneP p = dev::scene_params(a.prm);
     if (acc && exp)

@@ -35,7 +35,7 @@ class OrcaParams(ctypes.Structure):
                 ("neighbor_dist", ctypes.c_float), ("cell_size", ctypes.c_float),
                 ("max_neighbors", ctypes.c_int32), ("pref_is_goal", ctypes.c_int32),
                 ("f", (ctypes.c_float * 2) * 2), ("par_eps", ctypes.c_float),
-                ("accel", ctypes.c_float * 2)]
+                ("accel", ctypes.c_float * 2), ("turn", ctypes.c_float * 2)]
 
 
 class AgentsIn(ctypes.Structure):
@@ -174,6 +174,13 @@ def make_params(p) -> OrcaParams:
     acc = (0.0, 0.0) if acc is None else acc
     for c in range(2):
         out.accel[c] = float(acc[c])
+    try:
+        turn = g("turn")
+    except (AttributeError, KeyError):
+        turn = None
+    turn = (0.0, 0.0) if turn is None else turn
+    for c in range(2):
+        out.turn[c] = float(turn[c])
     return out
 
 
@@ -369,8 +376,8 @@ class Batch:
         raw = np.frombuffer(bytes(arr), dtype=np.uint8).copy()
         self.params = torch.as_tensor(raw).to(device)
         self.max_neighbors = max(int(make_params(p).max_neighbors) for p in scene_params)
-        self.has_accel = int(any(make_params(p).accel[c] > 0 for p in scene_params
-                                 for c in range(2)))
+        self.has_accel = int(any(make_params(p).accel[c] > 0 or make_params(p).turn[c] > 0
+                                 for p in scene_params for c in range(2)))
         self.mode = int(mode)
         self.block = int(block)    # lanes per workgroup (64, 128, 256; 0 = 128)
         self.k_tile = int(k_tile)  # compiled neighbour capacity (0 = smallest >= k)

@@ -43,6 +43,7 @@ class Params:
     f: tuple = F_PAPER
     par_eps: float = 1e-5
     accel: tuple = (0.0, 0.0)      # acceleration cap per class [m/s^2]; 0 = none
+    turn: tuple = (0.0, 0.0)       # turn-rate cap per class [rad/s]; 0 = none
 
     def as_dict(self) -> dict:
         return dataclasses.asdict(self)

@@ -86,17 +86,27 @@ def _accel(params):
     return (0.0, 0.0) if acc is None else tuple(float(np.float32(a)) for a in acc)
 
 
+def _turn(params):
+    t = params.get("turn") if isinstance(params, dict) else getattr(params, "turn", None)
+    return (0.0, 0.0) if t is None else tuple(float(np.float32(a)) for a in t)
+
+
+def _capped(params):
+    return any(a > 0 for a in _accel(params) + _turn(params))
+
+
 def _dt(params):
     return float(np.float32(params["dt"] if isinstance(params, dict) else params.dt))
 
 
 def hard_lines(st, params, a):
-    """Agent a's acceleration lines (k x 4, k = 0 or 8) and their centre,
-    from the oracle."""
-    acc = _accel(params)[int(st["cls"][a]) & 1]
+    """Agent a's hard lines -- its acceleration lines (0 or 8), then its
+    heading lines (0 or 2) -- and their centre, from the oracle."""
+    cls = int(st["cls"][a]) & 1
     v = (float(st["vx"][a]), float(st["vy"][a]))
     vmax = float(np.float32(st["max_speed"][a]))
-    h = oracle.accel_lines(v, vmax, acc, _dt(params))
+    h = np.concatenate([oracle.accel_lines(v, vmax, _accel(params)[cls], _dt(params)),
+                        oracle.turn_lines(v, _turn(params)[cls], _dt(params))])
     sp = float(np.hypot(*v))
     c = np.array(v) * (vmax / sp if sp > vmax else 1.0)
     return h, c
@@ -104,7 +114,7 @@ def hard_lines(st, params, a):
 
 def line_sensitive(o, st, idx, params=None, reps=4, rel=1e-6, seed=77):
     """For agents `idx`: whether the oracle LP answer on the agent's own
-    lines (acceleration lines, when capped, then half-planes) moves by more
+    lines (hard lines, when capped, then half-planes) moves by more
     than COND_TOL when every line component is scaled by (1 + U(-rel, rel))."""
     return line_movement(o, st, idx, params, reps, rel, seed) > COND_TOL
 
@@ -153,7 +163,7 @@ def penetration(lines, cnt, vx, vy):
 
 def valid_answer(o, g, vmax, tol=V_TOL, st=None, params=None):
     """Whether the GPU velocity solves the oracle's own FP64 problem to within
-    `tol`: inside the speed disc and the acceleration octagon (when capped),
+    `tol`: inside the speed disc and the hard lines (when capped),
     no more penetration of the half-planes than the oracle's answer (least
     penetration), and, when both sides found a permitted velocity, no
     farther from the desired velocity than the oracle's."""
@@ -161,7 +171,7 @@ def valid_answer(o, g, vmax, tol=V_TOL, st=None, params=None):
     pen_g = penetration(o["lines"], o["cnt"], vg_x, vg_y)
     pen_o = penetration(o["lines"], o["cnt"], o["vx"], o["vy"])
     speed_ok = np.hypot(vg_x, vg_y) <= vmax * (1 + 1e-5) + 1e-6
-    if params is not None and any(a > 0 for a in _accel(params)):
+    if params is not None and _capped(params):
         for a in range(len(vg_x)):
             hard, _ = hard_lines(st, params, a)
             if hard.shape[0]:

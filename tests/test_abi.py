@@ -33,7 +33,7 @@ def test_every_declared_symbol_is_exported(orca_mod):
 
 
 def test_struct_sizes_match_header(orca_mod):
-    assert ctypes.sizeof(orca_mod.OrcaParams) == 4 * 4 + 4 + 4 + 16 + 4 + 8
+    assert ctypes.sizeof(orca_mod.OrcaParams) == 4 * 4 + 4 + 4 + 16 + 4 + 8 + 8
     assert ctypes.sizeof(orca_mod.AgentsIn) == 9 * 8
     assert ctypes.sizeof(orca_mod.AgentsOut) == 5 * 8
     assert ctypes.sizeof(orca_mod.OrcaBatch) == 8 + 4 + 4 + 8 + 4 + 4 + 8 + 8 + 8
@@ -83,6 +83,8 @@ def _out_fake(orca_mod):
     (dict(cell_size=-1.0), -1), (dict(pref_is_goal=2), -1), (dict(par_eps=-1.0), -1),
     (dict(accel=(-1.0, 0.0)), -1), (dict(accel=(0.0, float("inf"))), -1),
     (dict(accel=(0.0, float("nan"))), -1),
+    (dict(turn=(-1.0, 0.0)), -1), (dict(turn=(0.0, float("inf"))), -1),
+    (dict(turn=(float("nan"), 0.0)), -1),
 ])
 def test_step_rejects_bad_params(orca_mod, kw, code):
     lib = orca_mod.lib()
@@ -206,6 +208,18 @@ def test_backward_accepts_acceleration_caps(orca_mod):
                                   ctypes.byref(g0), FAKE, 64, None) == -2
     assert lib.orca_step_backward(ctypes.byref(ain), 100, ctypes.byref(bad), ctypes.byref(g1),
                                   ctypes.byref(g0), FAKE, 64, None) == -1
+
+
+def test_backward_rejects_turn_caps(orca_mod):
+    """The heading wedge is not differentiated: the backward step refuses a
+    turn-rate cap before it looks at anything else."""
+    lib = orca_mod.lib()
+    ain = _in_fake(orca_mod)
+    g1 = orca_mod.Cotangents(*([FAKE] * 4))
+    g0 = orca_mod.CotangentsOut(*([FAKE] * 7))
+    turned = _params(orca_mod, turn=(0.0, 1.0))
+    assert lib.orca_step_backward(ctypes.byref(ain), 100, ctypes.byref(turned), ctypes.byref(g1),
+                                  ctypes.byref(g0), FAKE, 1 << 30, None) == -1
 
 
 def test_missing_library_fails_loudly(tmp_path):
