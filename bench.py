@@ -566,8 +566,8 @@ def bench_extensions(reps: int = 20):
     """The rows beyond the plain step, on the dense crossing's 1,048,576
     agents: leaving at the goal (orca_remove_arrived, a stable compaction,
     against HBM), entering (orca_spawn with 16,384 candidates), the overlap
-    statistics (orca_overlap_stats) and the step with acceleration caps
-    against the same step without them.  HIP events on the library's
+    statistics (orca_overlap_stats) and the step with acceleration caps and
+    with turn-rate caps against the same step without them.  HIP events on the library's
     stream (torch's current stream) around `reps` calls."""
     import dataclasses
     import numpy as np
@@ -636,10 +636,12 @@ def bench_extensions(reps: int = 20):
           "agents_per_s": n / (ov_ms * 1e-3)}
 
     # the dense crossing's step with acceleration caps (2 m/s^2 for everyone)
+    # and with turn-rate caps (1 rad/s for everyone)
     params = dataclasses.replace(sc.params, cell_size=0.6)
     capped = dataclasses.replace(params, accel=(2.0, 2.0))
+    turned = dataclasses.replace(params, turn=(1.0, 1.0))
     res = {}
-    for name, p in (("uncapped", params), ("capped", capped)):
+    for name, p in (("uncapped", params), ("capped", capped), ("turned", turned)):
         a = orca.State.from_arrays(sc)
         b = a.clone()
         ws = orca.Workspace(n)
@@ -655,10 +657,15 @@ def bench_extensions(reps: int = 20):
     ac = {"ms_per_step_capped": res["capped"], "ms_per_step_uncapped": res["uncapped"],
           "agent_steps_per_s_capped": n / (res["capped"] * 1e-3),
           "ratio": res["capped"] / res["uncapped"]}
+    tu = {"ms_per_step_turn_capped": res["turned"], "ms_per_step_uncapped": res["uncapped"],
+          "agent_steps_per_s_turn_capped": n / (res["turned"] * 1e-3),
+          "ratio": res["turned"] / res["uncapped"]}
     log(f"[bench] extensions: remove {rm_ms:.3f} ms ({rm['GBs']:.0f} GB/s), spawn {sp_ms:.3f} ms, "
-        f"overlap {ov_ms:.3f} ms, capped step {res['capped']:.3f} ms vs {res['uncapped']:.3f}")
+        f"overlap {ov_ms:.3f} ms, capped step {res['capped']:.3f} ms, turn-capped step "
+        f"{res['turned']:.3f} ms vs {res['uncapped']:.3f}")
     return {"metric": "ms per call on the 1,048,576-agent dense crossing",
-            "remove_arrived": rm, "spawn": sp, "overlap_stats": ov, "accel_step": ac}
+            "remove_arrived": rm, "spawn": sp, "overlap_stats": ov, "accel_step": ac,
+            "turn_step": tu}
 
 
 def bench_crossing():

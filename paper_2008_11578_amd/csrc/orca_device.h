@@ -1046,9 +1046,16 @@ __device__ __forceinline__ void lp3(const LdsLines<BLOCK, ACC> &ls, int m, int f
     // decide whether a later tied line triggers a re-solve, and the re-solve
     // then jumps to another vertex of the tie
     const float tol = vmax * FeasSlack<float>::v;
-    for (int i = fail > nhard ? fail : nhard; i < m; ++i) {
-        const float4 li = ls.line(i);
-        if (det2(li.z, li.w, li.x - x, li.y - y) <= level + tol) continue;
+    // as in lp2: each lane steps on to its own next line above the level, and
+    // the lanes re-solve together
+    int i = fail > nhard ? fail : nhard;
+    for (;;) {
+        float4 li;
+        for (; i < m; ++i) {
+            li = ls.line(i);
+            if (det2(li.z, li.w, li.x - x, li.y - y) > level + tol) break;
+        }
+        if (i >= m) break;
         ProjLines<BLOCK, ACC> src{ls, li, det2(li.z, li.w, li.x, li.y), eps};
         float nx = x, ny = y;
         ActiveSet inner;
@@ -1073,6 +1080,7 @@ __device__ __forceinline__ void lp3(const LdsLines<BLOCK, ACC> &ls, int m, int f
             }
         }
         level = det2(li.z, li.w, li.x - x, li.y - y);
+        ++i;
     }
     vx = x;
     vy = y;
