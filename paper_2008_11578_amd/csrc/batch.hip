@@ -39,10 +39,21 @@ __device__ __forceinline__ int scene_of(const int32_t *__restrict__ off, int S, 
 
 __device__ __forceinline__ int clamp_off(int v, int n) { return v < 0 ? 0 : (v > n ? n : v); }
 
-// (1) one block per scene: bounding box of its agents.  All blocks also clear
-// the histogram and block 0 the tile queues; scene offsets and parameters
-// are checked and any violation is flagged (the kernels stay in bounds
-// regardless: offsets are clamped to [0, n]).
+// Scene of caller index i given the scene s0 of an index <= i (off
+// ascending): a walk forward from s0, a step or two for the indices of one
+// tile, instead of a binary search per index.
+__device__ __forceinline__ int scene_from(const int32_t *__restrict__ off, int S, int s0, int i)
+{
+    int s = s0;
+    while (s + 1 < S && off[s + 1] <= i) ++s;
+    return s;
+}
+
+// (1) kBboxSplit blocks per scene: partial bounding boxes of its agents (a
+// block per scene left the largest scenes to one block each).  All blocks
+// also clear the histogram and block 0 the tile queues; scene offsets and
+// parameters are checked and any violation is flagged (the kernels stay in
+// bounds regardless: offsets are clamped to [0, n]).
 __global__ __launch_bounds__(kBlock) void k_batch_bbox(const float *__restrict__ px,
                                                        const float *__restrict__ py, int n,
                                                        const int32_t *__restrict__ off, int S,
@@ -53,10 +64,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_bbox(const float *__restrict__
                                                        int32_t *__restrict__ error_flag,
                                                        int has_accel)
 {
-    const int s = blockIdx.x;
+    const int s = blockIdx.x / kBboxSplit, part = blockIdx.x % kBboxSplit;
     const int a = clamp_off(off[s], n), b = clamp_off(off[s + 1], n);
     float4 bb = make_float4(INFINITY, INFINITY, -INFINITY, -INFINITY);
-    for (int i = a + threadIdx.x; i < b; i += kBlock) {
+    for (int i = a + part * kBlock + threadIdx.x; i < b; i += kBlock * kBboxSplit) {
         const float x = px[i], y = py[i];
         bb.x = fminf(bb.x, x);
         bb.y = fminf(bb.y, y);
@@ -68,8 +79,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_bbox(const float *__restrict__
     if (s == 0 && threadIdx.x < kXcds) queue[threadIdx.x] = 0u;
     bb = block_bbox<kBlock>(bb);
     if (threadIdx.x == 0) {
-        partial[s] = bb;
-        if (error_flag) {
+        partial[blockIdx.x] = bb;
+        if (error_flag && part == 0) {
             const orca_params p = prm[s];
             bool bad = off[s] > off[s + 1] || off[s] < 0 || off[s + 1] > n;
             if (s == 0) bad = bad || off[0] != 0;
@@ -108,8 +119,13 @@ __global__ __launch_bounds__(kBlock) void k_batch_setup(const float4 *__restrict
     const int a = clamp_off(off[s], n);
     const int b = max(clamp_off(off[s + 1], n), a);
     const int budget = 2 * (b - a) + 64;
+    float4 bb = partial[s * kBboxSplit];
+    for (int q = 1; q < kBboxSplit; ++q) {
+        const float4 p = partial[s * kBboxSplit + q];
+        bb = make_float4(fminf(bb.x, p.x), fminf(bb.y, p.y), fmaxf(bb.z, p.z), fmaxf(bb.w, p.w));
+    }
     GridMeta g;
-    grid_geometry(partial[s], prm[s].neighbor_dist, prm[s].cell_size, budget, g);
+    grid_geometry(bb, prm[s].neighbor_dist, prm[s].cell_size, budget, g);
     // a budget is 2 cells per agent plus 64; the cell ranges of consecutive
     // scenes tile the global cell space when offsets are valid and stay
     // inside it otherwise
@@ -155,14 +171,16 @@ struct BatchArgs {
 };
 
 template <int K, int BLOCK, bool ACC>
-__device__ __forceinline__ void batch_agent(const BatchArgs &a, int s, float4 *lines, int tid)
+__device__ __forceinline__ void batch_agent(const BatchArgs &a, int s, int first, float4 *lines,
+                                            int tid)
 {
-    const int sc = scene_of(a.off, a.S, s);
+    const int sc = scene_from(a.off, a.S, first, s);
     const GridMeta g = a.meta[sc];
     const dev::SceneP p = dev::scene_params(a.prm[sc]);
     dev::step_agent<K, BLOCK, ACC>(s, g, p, a.in, a.out, a.start, a.s0, a.s1, lines, tid,
                                    a.guess);
 }
+
 
 // Persistent step: wavefronts pop 64-agent tiles, first from their XCD's
 // queue (a contiguous eighth of the tiles), then from the others.
@@ -184,7 +202,9 @@ __global__ __launch_bounds__(BLOCK) void k_step_batched(BatchArgs a)
             t = __shfl(t, 0, kWave);
             if (t >= hi - lo) break;
             const int s = (lo + t) * kTile + lane;
-            if (s < a.n) batch_agent<K, BLOCK, ACC>(a, s, lines, tid);
+            // the tile's first scene, searched once (a wavefront-uniform index)
+            const int first = scene_of(a.off, a.S, (lo + t) * kTile);
+            if (s < a.n) batch_agent<K, BLOCK, ACC>(a, s, first, lines, tid);
         }
     }
 }
@@ -195,8 +215,9 @@ __global__ __launch_bounds__(BLOCK) void k_step_batched_flat(BatchArgs a)
 {
     __shared__ float4 lines[dev::KnnShape<K>::kSlots * BLOCK];
     const int tid = threadIdx.x;
-    const int s = xcd_tile(blockIdx.x, gridDim.x) * BLOCK + tid;
-    if (s < a.n) batch_agent<K, BLOCK, ACC>(a, s, lines, tid);
+    const int s0 = xcd_tile(blockIdx.x, gridDim.x) * BLOCK;
+    const int s = s0 + tid;
+    if (s < a.n) batch_agent<K, BLOCK, ACC>(a, s, scene_of(a.off, a.S, s0), lines, tid);
 }
 
 // Workgroups of k_step_batched that fit the device at once (cached per
@@ -265,7 +286,8 @@ hipError_t launch_batched(const orca_agents_in &in, const orca_agents_out &out, 
     const int nb = (n + kBlock - 1) / kBlock;
     if (ev && ev->grid_begin && hipEventRecord(ev->grid_begin, stream) != hipSuccess)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_batch_bbox, dim3(S), dim3(kBlock), 0, stream, in.px, in.py, n, scene_off,
+    hipLaunchKernelGGL(k_batch_bbox, dim3(S * kBboxSplit), dim3(kBlock), 0, stream, in.px, in.py,
+                       n, scene_off,
                        S, params, w.partial, w.count, (int)L.max_cells, w.queue, error_flag,
                        acc ? 1 : 0);
     hipLaunchKernelGGL(k_batch_setup, dim3((S + kBlock - 1) / kBlock), dim3(kBlock), 0, stream,

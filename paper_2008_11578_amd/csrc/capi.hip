@@ -29,7 +29,9 @@ Layout make_layout(int64_t n, int64_t n_scenes, int64_t max_cells)
     L.meta = o;
     o = align_up(o + sizeof(GridMeta) * (size_t)(S + 1));
     L.partial = o;
-    o = align_up(o + sizeof(float4) * (size_t)(S > kBboxBlocks ? S : kBboxBlocks));
+    const size_t n_partial = (size_t)S * kBboxSplit;
+    o = align_up(o + sizeof(float4) * (n_partial > (size_t)kBboxBlocks ? n_partial
+                                                                       : (size_t)kBboxBlocks));
     L.queue = o;
     o = align_up(o + sizeof(uint32_t) * kXcds);
     L.cell = o;

@@ -11,6 +11,7 @@ namespace orca {
 
 constexpr int kWave = 64;
 constexpr int kBboxBlocks = 1024;   // partial bounding boxes per scene (max)
+constexpr int kBboxSplit = 8;      // blocks (partial boxes) per scene of a batch
 constexpr int kScanTile = 2048;     // cells per scan tile (256 threads x 8)
 constexpr int kAlign = 256;
 constexpr int kScanPad = 16;        // float4 entries after the cell-ordered copy s0,
