@@ -744,7 +744,8 @@ def bench_adjoint(reps: int = 3, cpu: bool = True):
     def once():
         vpx = st0.pref_x.clone().requires_grad_(True)
         vpy = st0.pref_y.clone().requires_grad_(True)
-        tau = torch.tensor(float(np.float32(p.time_horizon)), device="cuda", requires_grad=True)
+        # a host scalar: the forward reads it without a device synchronisation
+        tau = torch.tensor(float(np.float32(p.time_horizon)), requires_grad=True)
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         e0.record()
         px, py = rollout.rollout(vpx, vpy, tau, st0, p, steps=steps, ckpt=10)
@@ -857,6 +858,9 @@ def main(argv=None):
                     help="skip the vehicle-share sweep of the mixed crowd")
     ap.add_argument("--no-legs", dest="legs", action="store_false",
                     help="skip the 256-agent and mixed-crowd configuration runs")
+    ap.add_argument("--calibrate-gather", type=int, default=0, metavar="MIB",
+                    help="only gather MIB of 16-byte records 5 times in a locally shuffled "
+                         "order (FETCH_SIZE calibration for the step's gathers)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (5 times) and exit: the "
                          "reference kernel for scaling HBM counters")
@@ -885,6 +889,23 @@ def main(argv=None):
             b.copy_(a)
         torch.cuda.synchronize()
         log(f"[bench] copied {args.calibrate_copy} MiB 5 times")
+        return 0
+    if args.calibrate_gather > 0:
+        # 16-byte records read in an order shuffled within windows of 4096
+        # records (every cache line is used whole, as the step's candidate
+        # rows use theirs), 32-bit indices, written in order
+        m = args.calibrate_gather << 16
+        src = torch.ones((m, 4), dtype=torch.float32, device="cuda")
+        g = torch.Generator(device="cpu").manual_seed(5)
+        win = 4096
+        perm = torch.cat([torch.randperm(win, generator=g) + w for w in range(0, m, win)])
+        idx = perm.to(torch.int32).cuda()
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            torch.index_select(src, 0, idx, out=dst)
+        torch.cuda.synchronize()
+        log(f"[bench] gathered {args.calibrate_gather} MiB 5 times ({m} records, "
+            f"{m * 16 + m * 4} bytes read per gather)")
         return 0
     sc = scenarios.c3_crossing(side_count=args.side)
     n = sc.n

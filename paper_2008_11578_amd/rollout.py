@@ -22,10 +22,12 @@ class Rollout(torch.autograd.Function):
     @staticmethod
     def forward(ctx, v_pref_x, v_pref_y, tau, state0: orca.State, params, steps: int, ckpt: int):
         # the step's scalar parameters travel by value to the kernels, so tau
-        # is read on the host once per rollout (one synchronisation when it
-        # lives on the device)
+        # is read on the host once per rollout: no synchronisation when it
+        # is a host tensor (its gradient is then returned on the host), one
+        # when it lives on the device
         p = dataclasses.replace(params, time_horizon=float(tau.detach().reshape(()).item()),
                                 pref_is_goal=0)
+        ctx.tau_device = tau.device
         n = state0.n
         st = state0.clone()
         st.pref_x = v_pref_x.detach().contiguous().clone()
@@ -88,7 +90,7 @@ class Rollout(torch.autograd.Function):
         if int(mismatch.item()) != 0:
             raise RuntimeError("rollout backward: a replayed segment left the forward trajectory "
                                f"({int(mismatch.item())} differing values)")
-        return g_prx, g_pry, g_tau.reshape(()), None, None, None, None
+        return g_prx, g_pry, g_tau.reshape(()).to(ctx.tau_device), None, None, None, None
 
 
 def rollout(v_pref_x: torch.Tensor, v_pref_y: torch.Tensor, tau: torch.Tensor,

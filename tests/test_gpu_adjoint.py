@@ -254,3 +254,30 @@ def test_rollout_gradient_full_shape_matches_oracle_chain():
     sc = scenarios.c5_rollout()
     e, exempt = _rollout_vs_chain(sc, sc.steps, 10, "rollout 16384 x 50")
     assert (e[~exempt] <= 1e-3).all()
+
+
+def test_rollout_host_tau_equals_device_tau():
+    """tau given as a host scalar (read without a device synchronisation)
+    gives the same rollout and the same gradients, bit for bit, as tau on
+    the device; its gradient comes back on the host."""
+    import torch
+    from paper_2008_11578_amd import orca, rollout
+    sc = scenarios.c5_rollout(n=2048, side=240.0 * np.sqrt(2048 / 16384))
+    p = sc.params
+    st0 = orca.State.from_arrays(sc)
+    tx = torch.as_tensor(sc.target_x).cuda()
+    ty = torch.as_tensor(sc.target_y).cuda()
+    res = []
+    for dev in ("cuda", "cpu"):
+        vpx = st0.pref_x.clone().requires_grad_(True)
+        vpy = st0.pref_y.clone().requires_grad_(True)
+        tau = torch.tensor(float(np.float32(p.time_horizon)), device=dev, requires_grad=True)
+        px, py = rollout.rollout(vpx, vpy, tau, st0, p, steps=12, ckpt=5)
+        loss = rollout.trajectory_loss(px, py, tx, ty)
+        loss.backward()
+        torch.cuda.synchronize()
+        assert tau.grad.device.type == dev
+        res.append((px.detach().cpu(), vpx.grad.cpu(), vpy.grad.cpu(), float(tau.grad)))
+    assert torch.equal(res[0][0], res[1][0])
+    assert torch.equal(res[0][1], res[1][1]) and torch.equal(res[0][2], res[1][2])
+    assert res[0][3] == res[1][3]
