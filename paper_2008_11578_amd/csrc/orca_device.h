@@ -279,11 +279,11 @@ __device__ __forceinline__ void sort_network(uint32_t (&e)[N])
 
 // Visits every candidate in the grid rows and chords of the circle of
 // squared radius r2 around (xd, yd), row by row and in cell order within a
-// row, in groups of kScanUnroll as visit(c, t, valid) (c = s0[t]), calling
-// group_end() after each group.  A group always loads all its members (the
-// last one of a row reads up to kScanUnroll - 1 entries past the row's end,
-// inside s0 and its padding) and passes valid = t < end of its row, so the
-// visitor runs without a remainder loop and can stay branch-free.
+// row, in groups of kScanUnroll as group(c, t0, e): c[q] = s0[t0 + q], a
+// member valid while t0 + q < e, the end of its row.  A group always loads
+// all its members (the last one of a row reads up to kScanUnroll - 1
+// entries past the row's end, inside s0 and its padding), so the visitor
+// runs without a remainder loop and can stay branch-free.
 //
 // The loop runs over groups, not rows, with the memory one step ahead of
 // the arithmetic: the next group -- the next one of the same row or the
@@ -296,10 +296,11 @@ __device__ __forceinline__ void sort_network(uint32_t (&e)[N])
 // per row would wait for the memory at every row.  A row whose range turns
 // out empty costs one group of invalid members.  Lanes step through their
 // own rows, so a wave runs as many groups as its busiest lane.
-template <class F, class G = NoGroupEnd>
-__device__ __forceinline__ void scan_disc(const GridMeta &g, const uint32_t *__restrict__ start,
-                                          const float4 *__restrict__ s0, double xd, double yd,
-                                          double r2, F &&visit, G &&group_end = G())
+template <class H>
+__device__ __forceinline__ void scan_disc_groups(const GridMeta &g,
+                                                 const uint32_t *__restrict__ start,
+                                                 const float4 *__restrict__ s0, double xd,
+                                                 double yd, double r2, H &&group)
 {
     int yr, yb;
     row_span(g, yd, r2, yr, yb);
@@ -355,9 +356,7 @@ __device__ __forceinline__ void scan_disc(const GridMeta &g, const uint32_t *__r
         // keep the loads ahead of the visit (the scheduler would otherwise
         // move them next to their use)
         __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int q = 0; q < kScanUnroll; ++q) visit(c[q], t0 + q, t0 + q < e0);
-        group_end();
+        group(c, t0, e0);
         if (!more1) break;
         const bool more2 = next_group(0, t1, e1, t0, e0);
         {
@@ -366,9 +365,7 @@ __device__ __forceinline__ void scan_disc(const GridMeta &g, const uint32_t *__r
             for (int q = 0; q < kScanUnroll; ++q) c[q] = pc[q];
         }
         __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int q = 0; q < kScanUnroll; ++q) visit(d[q], t1 + q, t1 + q < e1);
-        group_end();
+        group(d, t1, e1);
         if (!more2) break;
     }
     // the loads of the last pass are read on the way out too, so that the
@@ -377,6 +374,21 @@ __device__ __forceinline__ void scan_disc(const GridMeta &g, const uint32_t *__r
 #pragma unroll
     for (int q = 0; q < kScanUnroll; ++q)
         asm volatile("" ::"v"(c[q].x), "v"(c[q].y), "v"(d[q].x), "v"(d[q].y));
+}
+
+// The same scan with a visitor per candidate: visit(c, t, valid) for each
+// member of a group, then group_end().
+template <class F, class G = NoGroupEnd>
+__device__ __forceinline__ void scan_disc(const GridMeta &g, const uint32_t *__restrict__ start,
+                                          const float4 *__restrict__ s0, double xd, double yd,
+                                          double r2, F &&visit, G &&group_end = G())
+{
+    scan_disc_groups(g, start, s0, xd, yd, r2,
+                     [&](const float4 (&c)[kScanUnroll], uint32_t t0, uint32_t e) {
+#pragma unroll
+                         for (int q = 0; q < kScanUnroll; ++q) visit(c[q], t0 + q, t0 + q < e);
+                         group_end();
+                     });
 }
 
 // Selects the (at most K) nearest agents of the lane into entries [0, m) of
@@ -414,25 +426,36 @@ __device__ int knn_select(const GridMeta &g, const uint32_t *__restrict__ start,
         hod = 0;
         nib = 0;
         total = 0;
-        scan_disc(
+        scan_disc_groups(
             g, start, s0, xd, yd, r2c,
-            [&](const float4 &c, uint32_t t, bool valid) {
-                const double key = nb_key(xi, yi, c.x, c.y);
-                const bool in = valid && key < r2c;
-                // equals min((int)(key * bscale), kBins - 1) for every key, and
-                // is defined also for the far (or invalid) candidates it is not
-                // used for
-                const int bin = (int)fmin(key * bscale, (double)(kBins - 1));
-                nib += (uint64_t)(in ? 1u : 0u) << (bin * 4);
-                // branch-free, so that the candidates of a group form one
-                // block: every candidate is written at the next free slot and
-                // kept only when in range; once the buffer is full the writes
-                // land on its last slot, the only one they can overwrite
-                const int slot = total < (uint32_t)(kCap - 1) ? (int)total : kCap - 1;
-                buf[buf_idx<BLOCK>(slot, tid)] = pack_entry(key, t, (uint32_t)bin);
-                total += in ? 1u : 0u;
-            },
-            [&]() {
+            [&](const float4 (&c)[kScanUnroll], uint32_t t0, uint32_t e) {
+                // the keys of the whole group first (independent of one
+                // another, so their FP64 chains interleave), then the
+                // counters and the buffer in member order
+                double key[kScanUnroll];
+                int bin[kScanUnroll];
+                bool in[kScanUnroll];
+#pragma unroll
+                for (int q = 0; q < kScanUnroll; ++q) {
+                    key[q] = nb_key(xi, yi, c[q].x, c[q].y);
+                    in[q] = t0 + q < e && key[q] < r2c;
+                    // equals min((int)(key * bscale), kBins - 1) for every
+                    // key, and is defined also for the far (or invalid)
+                    // candidates it is not used for
+                    bin[q] = (int)fmin(key[q] * bscale, (double)(kBins - 1));
+                }
+#pragma unroll
+                for (int q = 0; q < kScanUnroll; ++q) {
+                    nib += (uint64_t)(in[q] ? 1u : 0u) << (bin[q] * 4);
+                    // branch-free, so that the candidates of a group form one
+                    // block: every candidate is written at the next free slot
+                    // and kept only when in range; once the buffer is full the
+                    // writes land on its last slot, the only one they can
+                    // overwrite
+                    const int slot = total < (uint32_t)(kCap - 1) ? (int)total : kCap - 1;
+                    buf[buf_idx<BLOCK>(slot, tid)] = pack_entry(key[q], t0 + q, (uint32_t)bin[q]);
+                    total += in[q] ? 1u : 0u;
+                }
                 hev += nib & 0x0F0F0F0F0F0F0F0Full;
                 hod += (nib >> 4) & 0x0F0F0F0F0F0F0F0Full;
                 nib = 0;
