@@ -111,8 +111,9 @@ typedef struct {
                              at the origin.  The wedge's two sides are hard
                              lines after the acceleration lines.  An agent at
                              rest has no heading and no wedge.
-                             orca_step_backward rejects turn > 0 (ORCA_EINVAL):
-                             the wedge is not differentiated. */
+                             orca_step_backward differentiates the wedge
+                             through the heading v/|v| (turn and dt are
+                             constants). */
 } orca_params;
 
 /* Bytes of workspace needed for n agents (plain step / grid), or for a

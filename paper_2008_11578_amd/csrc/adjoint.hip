@@ -192,7 +192,11 @@ __device__ __forceinline__ void adjoint_agent(int s, const AdjArgs &a, const Gri
         pos[q] = q < m ? dev::entry_pos(buf[dev::buf_idx<BLOCK>(q, tid)]) : 0u;
     const float vmax = a.in.max_speed[i];
     const float acc = ACC ? (ci ? p.acc1 : p.acc0) : 0.0f;
-    const int nh = (ACC && acc > 0.0f) ? dev::kAccLines : 0;
+    const float turn = ACC ? (ci ? p.turn1 : p.turn0) : 0.0f;
+    const int nacc = (ACC && acc > 0.0f) ? dev::kAccLines : 0;
+    float rx = 0.0f, ry = 0.0f, lx = 0.0f, ly = 0.0f;
+    const int nh = nacc + ((ACC && dev::turn_wedge(vxi, vyi, turn, p.dt, rx, ry, lx, ly))
+                               ? dev::kTurnLines : 0);
     dev::build_halfplanes<K, BLOCK>(pos, m, a.s0, a.s1, xi, yi, vxi, vyi, ri, i, ci, p, lines,
                                     tid);
     float cx = 0.0f, cy = 0.0f;
@@ -208,7 +212,8 @@ __device__ __forceinline__ void adjoint_agent(int s, const AdjArgs &a, const Gri
         d2g = gxg * gxg + gyg * gyg;
     }
     const dev::LdsLines<BLOCK, ACC> src{lines, tid, nh, cx, cy,
-                                        ACC && nh ? dev::accel_half_width(acc, p.dt) : 0.0f};
+                                        ACC && nacc ? dev::accel_half_width(acc, p.dt) : 0.0f,
+                                        nacc, rx, ry, lx, ly};
     float vx, vy;
     dev::ActiveSet rec{dev::kFree, -1, -1, -1};
     const int mt = nh + m;
@@ -235,6 +240,7 @@ __device__ __forceinline__ void adjoint_agent(int s, const AdjArgs &a, const Gri
     }
     float pbx = 0.0f, pby = 0.0f;  // cotangent of the desired velocity
     float cbx = 0.0f, cby = 0.0f;  // cotangent of the acceleration octagon's centre
+    float hbx = 0.0f, hby = 0.0f;  // cotangent of the heading (turn wedge)
     auto Lq = [&](int idx) { return src.line(idx); };
     // Rows of an LP3 sub-problem: line j < nh is a hard line, g = n_j,
     // r = n_j . q_j; otherwise the equal-penetration boundary of j and i3,
@@ -370,10 +376,24 @@ __device__ __forceinline__ void adjoint_agent(int s, const AdjArgs &a, const Gri
     for (int e = 0; e < kEdges; ++e) {
         int32_t tgt = -1;
         float4 val = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (ACC && lb.idx[e] >= 0 && lb.idx[e] < nh) {
+        if (ACC && lb.idx[e] >= 0 && lb.idx[e] < nacc) {
             // acceleration line: q = c + h n_k with a constant normal
             cbx += lb.qx[e];
             cby += lb.qy[e];
+        } else if (ACC && lb.idx[e] >= nacc && lb.idx[e] < nh) {
+            // wedge side: q = 0, d = R(-phi) h (right) or -R(phi) h (left);
+            // n = (-d.y, d.x), so d-bar = (n-bar.y, -n-bar.x), and h-bar =
+            // R(phi) d-bar (right) or -R(-phi) d-bar (left)
+            float hx, hy, cs, sn, speed;
+            dev::turn_basis(vxi, vyi, turn, p.dt, hx, hy, cs, sn, speed);
+            const float dbx = lb.ny[e], dby = -lb.nx[e];
+            if (lb.idx[e] == nacc) {
+                hbx += cs * dbx - sn * dby;
+                hby += sn * dbx + cs * dby;
+            } else {
+                hbx -= cs * dbx + sn * dby;
+                hby -= -sn * dbx + cs * dby;
+            }
         } else if (lb.idx[e] >= 0) {
             uint32_t pj = 0u;
             const int qn = lb.idx[e] - nh;
@@ -399,6 +419,14 @@ __device__ __forceinline__ void adjoint_agent(int s, const AdjArgs &a, const Gri
         }
         a.e_tgt[(int64_t)kEdges * i + e] = tgt;
         a.e_val[(int64_t)kEdges * i + e] = val;
+    }
+    if (ACC && nh > nacc) {
+        // h = v / |v|: Jacobian (I - h h^T) / |v|
+        float hx, hy, cs, sn, speed;
+        dev::turn_basis(vxi, vyi, turn, p.dt, hx, hy, cs, sn, speed);
+        const float hh = hx * hbx + hy * hby;
+        svx += (hbx - hx * hh) / speed;
+        svy += (hby - hy * hh) / speed;
     }
     if (ACC && nh) {
         // c = v, or v (v_max / |v|) when |v| > v_max: Jacobian (v_max/|v|)(I - u u^T)
@@ -606,7 +634,7 @@ template <int K>
 void launch_adjoint_k(const AdjArgs &a, hipStream_t stream)
 {
     const int nb = (a.n + kAdjBlock - 1) / kAdjBlock;
-    if (a.p.acc0 > 0.0f || a.p.acc1 > 0.0f)
+    if (a.p.acc0 > 0.0f || a.p.acc1 > 0.0f || a.p.turn0 > 0.0f || a.p.turn1 > 0.0f)
         hipLaunchKernelGGL((k_adjoint<K, kAdjBlock, true>), dim3(nb), dim3(kAdjBlock), 0, stream,
                            a);
     else

@@ -390,8 +390,6 @@ int orca_step_backward_ex(const orca_agents_in *in, int32_t n, const orca_params
     if (n < 0 || n > ORCA_N_MAX) return ORCA_EINVAL;
     int rc = check_params(params);
     if (rc != ORCA_OK) return rc;
-    // the heading wedge is not differentiated
-    if (params->turn[0] > 0.0f || params->turn[1] > 0.0f) return ORCA_EINVAL;
     if (n == 0) return ORCA_OK;
     rc = check_in(in);
     if (rc != ORCA_OK) return rc;

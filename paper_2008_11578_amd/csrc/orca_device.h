@@ -728,16 +728,28 @@ __device__ __forceinline__ float4 accel_line(int k, float cx, float cy, float h)
 // constraints after any acceleration lines.  Returns false at rest (no
 // heading, no wedge).  The heading is formed in double, so that a speed
 // whose square underflows FP32 still has one.
-__device__ __forceinline__ bool turn_wedge(float vx, float vy, float turn, float dt, float &rx,
-                                           float &ry, float &lx, float &ly)
+// The heading h = v/|v| and the wedge's cos(phi), sin(phi); false at rest.
+// `speed` is |v| (for the adjoint's Jacobian of h).
+__device__ __forceinline__ bool turn_basis(float vx, float vy, float turn, float dt, float &hx,
+                                           float &hy, float &cs, float &sn, float &speed)
 {
     const double v2 = (double)vx * vx + (double)vy * vy;
     if (!(turn > 0.0f) || !(v2 > 0.0)) return false;
-    const double inv = 1.0 / sqrt(v2);
-    const float hx = (float)(vx * inv), hy = (float)(vy * inv);
+    const double sp = sqrt(v2);
+    const double inv = 1.0 / sp;
+    hx = (float)(vx * inv);
+    hy = (float)(vy * inv);
+    speed = (float)sp;
     const float phi = fminf(turn * dt, 1.57079633f);
-    float sn, cs;
     sincosf(phi, &sn, &cs);
+    return true;
+}
+
+__device__ __forceinline__ bool turn_wedge(float vx, float vy, float turn, float dt, float &rx,
+                                           float &ry, float &lx, float &ly)
+{
+    float hx, hy, cs, sn, speed;
+    if (!turn_basis(vx, vy, turn, dt, hx, hy, cs, sn, speed)) return false;
     rx = hx * cs + hy * sn;
     ry = hy * cs - hx * sn;
     lx = -(hx * cs - hy * sn);

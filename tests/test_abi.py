@@ -210,16 +210,18 @@ def test_backward_accepts_acceleration_caps(orca_mod):
                                   ctypes.byref(g0), FAKE, 64, None) == -1
 
 
-def test_backward_rejects_turn_caps(orca_mod):
-    """The heading wedge is not differentiated: the backward step refuses a
-    turn-rate cap before it looks at anything else."""
+def test_backward_accepts_turn_caps(orca_mod):
     lib = orca_mod.lib()
     ain = _in_fake(orca_mod)
     g1 = orca_mod.Cotangents(*([FAKE] * 4))
     g0 = orca_mod.CotangentsOut(*([FAKE] * 7))
     turned = _params(orca_mod, turn=(0.0, 1.0))
+    bad = _params(orca_mod, turn=(0.0, -1.0))
+    # a valid cap gets past the parameter checks (small workspace), a negative one does not
     assert lib.orca_step_backward(ctypes.byref(ain), 100, ctypes.byref(turned), ctypes.byref(g1),
-                                  ctypes.byref(g0), FAKE, 1 << 30, None) == -1
+                                  ctypes.byref(g0), FAKE, 64, None) == -2
+    assert lib.orca_step_backward(ctypes.byref(ain), 100, ctypes.byref(bad), ctypes.byref(g1),
+                                  ctypes.byref(g0), FAKE, 64, None) == -1
 
 
 def test_missing_library_fails_loudly(tmp_path):

@@ -163,3 +163,64 @@ def test_batched_flags_turn_caps_without_the_capped_kernel():
     orca.step_batched(st, b, orca.Workspace(sc.n, n_scenes=1))
     torch.cuda.synchronize()
     assert int(b.error.item()) == 1
+
+
+@pytest.mark.parametrize("turn", [(1.0, 1.0), (2.0, 0.0)])
+def test_turn_capped_step_backward_matches_oracle(turn):
+    """The adjoint through the heading wedge (sides along R(-+phi) v/|v|)
+    against the oracle's forward-mode gradient, from a state where the
+    wedges bind for many agents; touching agents are left out of the
+    position check as in the acceleration case.  (Wedges much narrower than
+    these -- 0.03 rad per step -- put LP vertices so close together that
+    the active set, and with it the derivative, flips for some agents under
+    FP32-sized perturbations of the state: the oracle's own gradient then
+    moves by whole units there.)"""
+    import torch
+    from paper_2008_11578_amd import orca
+    from test_gpu_accel import _rel
+    sc = scenarios.c5_rollout(seed=7, n=4096, side=120.0)
+    params = dataclasses.replace(sc.params, turn=turn)
+    st = orca.State.from_arrays(sc)
+    nxt = st.clone()
+    ws = orca.Workspace(st.n)
+    for _ in range(6):
+        orca.step(st, params, ws, out=nxt)
+        st, nxt = nxt, st
+    torch.cuda.synchronize()
+    S = st.to_numpy()
+    o_cap = oracle.step(S, params)
+    o_free = oracle.step(S, dataclasses.replace(params, turn=(0.0, 0.0)))
+    bind = np.hypot(o_cap["vx"] - o_free["vx"], o_cap["vy"] - o_free["vy"]) > 1e-4
+    _print("turn", turn, "wedge binds for", int(bind.sum()), "of", st.n)
+    assert bind.mean() > 0.05
+    rng = np.random.default_rng(14)
+    cot = [rng.normal(size=st.n).astype(np.float32) for _ in range(4)]
+    g = [torch.as_tensor(c).cuda() for c in cot]
+    gpr = torch.zeros(st.n, device="cuda")
+    gpy = torch.zeros(st.n, device="cuda")
+    gt = torch.zeros(1, device="cuda")
+    out = orca.step_backward(st, params, orca.Workspace(st.n, backward=True), *g, gpr, gpy, gt)
+    torch.cuda.synchronize()
+    gpx, gpy0, gvx, gvy = [t.cpu().numpy() for t in out]
+    o = oracle.step_vjp(S, params, *[c.astype(np.float64) for c in cot])
+    on = oracle.step(S, params, want_neighbors=True)
+    gap = np.full(st.n, np.inf)
+    for q in range(on["nbr"].shape[1]):
+        j = on["nbr"][:, q]
+        ok = (j >= 0) & (q < on["cnt"])
+        jj = np.where(ok, j, 0)
+        d = np.hypot(S["px"][jj].astype(np.float64) - S["px"],
+                     S["py"][jj].astype(np.float64) - S["py"])
+        r = S["radius"].astype(np.float64) + S["radius"][jj]
+        gap = np.where(ok, np.minimum(gap, d - r), gap)
+    keep = ~(np.abs(gap) < 1e-4)
+    assert keep.mean() > 0.99
+    for a, k, tol, mask in ((gvx, "g_vx", 1e-4, None), (gvy, "g_vy", 1e-4, None),
+                            (gpr.cpu().numpy(), "g_pref_x", 1e-4, None),
+                            (gpy.cpu().numpy(), "g_pref_y", 1e-4, None),
+                            (gpx, "g_px", 5e-3, keep), (gpy0, "g_py", 5e-3, keep)):
+        ref = o[k] if mask is None else o[k][mask]
+        a = a if mask is None else a[mask]
+        _print(k, _rel(a, ref))
+        assert _rel(a, ref) <= tol, (k, _rel(a, ref))
+        assert np.max(np.abs(a - ref)) <= 1e-3 * np.max(np.abs(ref)), k
