@@ -760,6 +760,27 @@ def bench_adjoint(reps: int = 3, cpu: bool = True):
     runs = [once() for _ in range(reps)]
     fwd = float(np.median([r[0] for r in runs]))
     bwd = float(np.median([r[1] for r in runs]))
+    # the same rollout captured in HIP graphs (forward; backward with its
+    # segment replays): replays with the desired velocities and the loss's
+    # cotangents as inputs
+    rg = rollout.RolloutGraph(st0, p, float(np.float32(p.time_horizon)), steps=steps, ckpt=10)
+    gtimes = []
+    for _ in range(reps + 1):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        gx, gy = rg.forward(st0.pref_x, st0.pref_y)
+        e1.record()
+        cx = (2.0 / n) * (gx - tx)
+        cy = (2.0 / n) * (gy - ty)
+        rg.g_px.copy_(cx)
+        rg.g_py.copy_(cy)
+        rg.g_bwd.replay()
+        e2.record()
+        torch.cuda.synchronize()
+        gtimes.append((e0.elapsed_time(e1), e1.elapsed_time(e2)))
+    rg.backward(cx, cy)  # the replayed segments end where the forward went
+    fwd_g = float(np.median([t[0] for t in gtimes[1:]]))
+    bwd_g = float(np.median([t[1] for t in gtimes[1:]]))
     # the adjoint kernel alone over the rollout's trajectory
     import dataclasses
     pv = dataclasses.replace(p, pref_is_goal=0)
@@ -784,12 +805,15 @@ def bench_adjoint(reps: int = 3, cpu: bool = True):
     k_ms = float(np.mean([hip.elapsed_ms(e[1], e[2]) for e in pre]))
     hip.close()
     log(f"[bench] adjoint {n} agents x {steps} steps: forward {fwd:.2f} ms, backward {bwd:.2f} ms, "
-        f"adjoint kernel {k_ms * 1e3:.1f} us")
+        f"adjoint kernel {k_ms * 1e3:.1f} us; captured: forward {fwd_g:.2f} ms, "
+        f"backward {bwd_g:.2f} ms")
     out = {"metric": "agent-steps/s of a differentiable rollout (forward + backward)",
            "agents": n, "steps": steps, "checkpoint_every": 10, "forward_ms": fwd,
            "backward_ms": bwd, "adjoint_kernel_ms": k_ms,
            "agent_steps_per_s": n * steps / ((fwd + bwd) * 1e-3),
            "backward_agent_steps_per_s": n * steps / (bwd * 1e-3),
+           "captured": {"forward_ms": fwd_g, "backward_ms": bwd_g,
+                        "agent_steps_per_s": n * steps / ((fwd_g + bwd_g) * 1e-3)},
            "loss": runs[-1][2], "dL_dtau": runs[-1][3]}
     if cpu:
         import oracle

@@ -281,3 +281,36 @@ def test_rollout_host_tau_equals_device_tau():
     assert torch.equal(res[0][0], res[1][0])
     assert torch.equal(res[0][1], res[1][1]) and torch.equal(res[0][2], res[1][2])
     assert res[0][3] == res[1][3]
+
+
+def test_rollout_graph_replays_equal_eager_rollout():
+    """The captured rollout (forward and backward graphs) gives the eager
+    rollout's final positions and gradients bit for bit, on two replays with
+    different desired velocities (with eager work in between)."""
+    import torch
+    from paper_2008_11578_amd import orca, rollout
+    sc = scenarios.c5_rollout(n=2048, side=240.0 * np.sqrt(2048 / 16384))
+    p = sc.params
+    st0 = orca.State.from_arrays(sc)
+    tx = torch.as_tensor(sc.target_x).cuda()
+    ty = torch.as_tensor(sc.target_y).cuda()
+    tau = float(np.float32(p.time_horizon))
+    rg = rollout.RolloutGraph(st0, p, tau, steps=12, ckpt=5)
+    for r in range(2):
+        scale = 1.0 - 0.1 * r
+        vpx = (st0.pref_x * scale).clone().requires_grad_(True)
+        vpy = (st0.pref_y * scale).clone().requires_grad_(True)
+        tt = torch.tensor(tau, requires_grad=True)
+        px, py = rollout.rollout(vpx, vpy, tt, st0, p, steps=12, ckpt=5)
+        # the cotangents autograd hands the rollout, for the graph's backward
+        seen = {}
+        px.register_hook(lambda g: seen.__setitem__("x", g.clone()))
+        py.register_hook(lambda g: seen.__setitem__("y", g.clone()))
+        rollout.trajectory_loss(px, py, tx, ty).backward()
+        torch.cuda.synchronize()
+        gx, gy = rg.forward(vpx.detach(), vpy.detach())
+        assert torch.equal(gx, px.detach()) and torch.equal(gy, py.detach()), r
+        g_prx, g_pry, g_tau = rg.backward(seen["x"], seen["y"])
+        torch.cuda.synchronize()
+        assert torch.equal(g_prx, vpx.grad) and torch.equal(g_pry, vpy.grad), r
+        assert float(g_tau) == float(tt.grad), r
