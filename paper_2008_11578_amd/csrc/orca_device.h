@@ -871,6 +871,57 @@ struct ProjLinesD {
     }
 };
 
+// The boundaries of one least-penetration sub-problem, cached in the LDS
+// column of a lane of the same wavefront that runs no LP3 (its half-planes
+// are not read again once its LP2 is done): lp3 computes the boundaries
+// j < i of line i once, and the lp1 calls of the sub-problem read them
+// instead of recomputing every one at each re-solve.  A cached boundary is
+// the value ProjLines computes (multiply-adds are fused within an expression
+// only, so it has the bits of one computed where it is used), so the result
+// is the same bit for bit with or without a column; a lane without one (a
+// wavefront with more lanes in LP3 than not) computes on demand.
+template <int BLOCK, bool ACC>
+struct CachedProj {
+    const ProjLines<BLOCK, ACC> &pl;
+    const float4 *L;  // the workgroup's [slot][BLOCK] array
+    int col;          // cache column, or -1
+    uint32_t valid;   // bit j: boundary j is a constraint
+    __device__ __forceinline__ bool get(int j, float4 &out) const
+    {
+        if (col >= 0) {
+            out = L[j * BLOCK + col];
+            return (valid >> j) & 1u;
+        }
+        return pl.get(j, out);
+    }
+};
+
+// The cache column of this lane for lp3 (CachedProj): the r-th lane of the
+// wavefront that needs LP3 (in lane order) takes the column of the r-th lane
+// that does not; -1 without one.  Every active lane of the wavefront calls
+// it, after its LP2; the columns handed out are not read by their owners
+// again in this step.
+template <int BLOCK>
+__device__ __forceinline__ int lp3_cache_column(bool need, int tid)
+{
+    const uint64_t needm = __ballot(need);
+    uint64_t spare = __ballot(!need);
+    const int lane = tid & (kWave - 1);
+    int col = -1;
+    if (need) {
+        int r = __popcll(needm & ((1ull << lane) - 1ull));
+        if (r < __popcll(spare)) {
+            for (; r > 0; --r) spare &= spare - 1ull;
+            col = (tid - lane) + __builtin_ctzll(spare);
+        }
+    }
+    // the owners' last reads of those columns (their LP2) stay before the
+    // cache writes of other lanes
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    return col;
+}
+
 // The constraints that define an LP result (its active set), recorded by
 // the adjoint's recomputation of the step.  LP2 results: kFree (v = v_pref),
 // kDisc (v_pref scaled onto the speed circle), kLine (projection of v_pref
@@ -1067,11 +1118,14 @@ __device__ __forceinline__ int lp2(const Src &src, int m, S vmax, int mode, S ox
 // region where no earlier line penetrates more than line i, as deep into line
 // i's permitted side as possible.  With ACC the first nh lines are hard: never
 // relaxed, they bound every re-solve as they are.
+// `col`: a cache column for the sub-problems' boundaries (lp3_cache_column;
+// only without hard lines), or -1.
 template <bool REC, int BLOCK, bool ACC = false>
 __device__ __forceinline__ void lp3(const LdsLines<BLOCK, ACC> &ls, int m, int fail, float vmax,
                                     float tx, float ty, float eps, float &vx, float &vy,
-                                    ActiveSet *rec)
+                                    ActiveSet *rec, int col = -1)
 {
+    static_assert(ORCA_K_MAX <= 32, "the cache's validity bits are one 32-bit word");
     float level = 0.0f;
     float x = vx, y = vy;
     const int nhard = ACC ? ls.nh : 0;
@@ -1092,9 +1146,19 @@ __device__ __forceinline__ void lp3(const LdsLines<BLOCK, ACC> &ls, int m, int f
         }
         if (i >= m) break;
         ProjLines<BLOCK, ACC> src{ls, li, det2(li.z, li.w, li.x, li.y), eps};
+        uint32_t valid = 0;
+        if (!ACC && col >= 0) {
+            float4 *C = const_cast<float4 *>(ls.L);
+            for (int j = 0; j < i; ++j) {
+                float4 b;
+                valid |= (src.get(j, b) ? 1u : 0u) << j;
+                C[j * BLOCK + col] = b;
+            }
+        }
+        const CachedProj<BLOCK, ACC> cs{src, ls.L, ACC ? -1 : col, valid};
         float nx = x, ny = y;
         ActiveSet inner;
-        bool solved = lp2<REC, float>(src, i, vmax, 1, -li.w, li.z, tx, ty, eps, nx, ny,
+        bool solved = lp2<REC, float>(cs, i, vmax, 1, -li.w, li.z, tx, ty, eps, nx, ny,
                                       &inner) == i;
         if (!solved) {
             // failed in FP32 only: solve it again in double (ProjLinesD)
@@ -1212,8 +1276,10 @@ __device__ __forceinline__ void desired_velocity(const SceneP &p, float xi, floa
 // pass.  ACC compiles the acceleration lines in (used for agents whose class
 // has a cap).  EXPORT also writes the neighbour list the step used (caller
 // indices, ascending, -1 padded) to nbr[i * kout ..] and its length to
-// cnt[i] (either nullable); the step itself is unchanged.
-template <int K, int BLOCK, bool ACC = false, bool EXPORT = false>
+// cnt[i] (either nullable); the step itself is unchanged.  LP3CACHE lets
+// LP3 cache its sub-problems' boundaries in spare LDS columns (CachedProj;
+// without hard lines), which changes no result.
+template <int K, int BLOCK, bool ACC = false, bool EXPORT = false, bool LP3CACHE = false>
 __device__ __forceinline__ void step_agent(int s, const GridMeta &g, const SceneP &p,
                                            const orca_agents_in &in, const orca_agents_out &out,
                                            const uint32_t *__restrict__ start,
@@ -1289,8 +1355,9 @@ __device__ __forceinline__ void step_agent(int s, const GridMeta &g, const Scene
         fail = nh;
         st = 1;
     }
+    const int col = (ACC || !LP3CACHE) ? -1 : lp3_cache_column<BLOCK>(fail < mt, tid);
     if (fail < mt) {
-        lp3<false, BLOCK, ACC>(src, mt, fail, vmax, prx, pry, p.eps, vx, vy, nullptr);
+        lp3<false, BLOCK, ACC>(src, mt, fail, vmax, prx, pry, p.eps, vx, vy, nullptr, col);
         st = 1;
     }
     out.vx[i] = vx;
