@@ -496,8 +496,8 @@ __global__ __launch_bounds__(kBlock) void k_edge_count(const int32_t *__restrict
 }
 
 // Exclusive scan of the per-target counts in tiles of kScanTile: the sum of
-// each tile, one block scanning the tile sums, then the scan inside each
-// tile offset by its prefix.
+// each tile, then the scan inside each tile offset by its prefix, the sum of
+// the tile sums before it (added up by each block itself).
 constexpr int kPer = kScanTile / kBlock;
 
 __global__ __launch_bounds__(kBlock) void k_escan_reduce(const uint32_t *__restrict__ cnt, int n,
@@ -515,25 +515,15 @@ __global__ __launch_bounds__(kBlock) void k_escan_reduce(const uint32_t *__restr
     if (threadIdx.x == 0) tiles[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(kBlock) void k_escan_tiles(uint32_t *__restrict__ tiles, int nt)
-{
-    uint32_t carry = 0;
-    for (int b = 0; b < nt; b += kBlock) {
-        const int t = b + threadIdx.x;
-        const uint32_t v = t < nt ? tiles[t] : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan<kBlock>(v, &tot);
-        if (t < nt) tiles[t] = carry + ex;
-        carry += tot;
-        __syncthreads();
-    }
-}
-
 __global__ __launch_bounds__(kBlock) void k_escan_apply(const uint32_t *__restrict__ cnt, int n,
                                                         const uint32_t *__restrict__ tiles,
                                                         uint32_t *__restrict__ start)
 {
     const int base = blockIdx.x * kScanTile;
+    uint32_t before = 0;
+    for (int t = threadIdx.x; t < (int)blockIdx.x; t += kBlock) before += tiles[t];
+    uint32_t prefix;
+    block_excl_scan<kBlock>(before, &prefix);
     uint32_t v[kPer];
     uint32_t s = 0;
 #pragma unroll
@@ -543,7 +533,7 @@ __global__ __launch_bounds__(kBlock) void k_escan_apply(const uint32_t *__restri
         s += v[k];
     }
     uint32_t tot;
-    uint32_t run = tiles[blockIdx.x] + block_excl_scan<kBlock>(s, &tot);
+    uint32_t run = prefix + block_excl_scan<kBlock>(s, &tot);
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         const int c = base + threadIdx.x * kPer + k;
@@ -701,7 +691,6 @@ hipError_t launch_adjoint(const orca_agents_in &in, int n, const orca_params &pr
                        b.e_rank);
     const int nt = (n + kScanTile - 1) / kScanTile;
     hipLaunchKernelGGL(k_escan_reduce, dim3(nt), dim3(kBlock), 0, stream, b.e_cnt, n, b.e_tiles);
-    hipLaunchKernelGGL(k_escan_tiles, dim3(1), dim3(kBlock), 0, stream, b.e_tiles, nt);
     hipLaunchKernelGGL(k_escan_apply, dim3(nt), dim3(kBlock), 0, stream, b.e_cnt, n, b.e_tiles,
                        b.e_start);
     hipLaunchKernelGGL(k_edge_place, dim3(nbe), dim3(kBlock), 0, stream, b.e_tgt, ne, n, b.e_rank,

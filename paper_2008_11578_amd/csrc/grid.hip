@@ -12,6 +12,9 @@ namespace orca {
 namespace {
 
 constexpr int kBlock = 256;
+// Crowds whose bounding box takes at most this many blocks of (1) form the
+// grid geometry inside (3) (see k_cell_count).
+constexpr int kFusedParts = 128;
 
 // (1) partial bounding boxes; also clears the cell histogram for (3).
 __global__ __launch_bounds__(kBlock) void k_bbox_partial(const float *__restrict__ px,
@@ -61,17 +64,53 @@ __global__ __launch_bounds__(kBlock) void k_grid_setup(const float4 *__restrict_
     *meta = g;
 }
 
-// (3) cell key and rank inside the cell (atomic counting).
+// (3) cell key and rank inside the cell (atomic counting).  With `partial`
+// (small crowds, at most kFusedParts boxes from (1)) every block also does
+// (2) itself: it combines the boxes and forms the geometry (grid_geometry,
+// the same bits in every block), and block 0 stores it for the kernels
+// after this one; a crowd of 16,384 agents then saves the one-block launch.
+// Without it (large crowds, whose (1) runs many more blocks than a block of
+// (3) could combine cheaply) the geometry comes from (2) through `meta`.
 __global__ __launch_bounds__(kBlock) void k_cell_count(const float *__restrict__ px,
                                                        const float *__restrict__ py, int n,
-                                                       const GridMeta *__restrict__ meta,
+                                                       const float4 *__restrict__ partial,
+                                                       int n_partial, float rn, float cs_req,
+                                                       int max_cells,
+                                                       const float *__restrict__ rn_dev,
+                                                       GridMeta *__restrict__ meta,
                                                        uint32_t *__restrict__ cell,
                                                        uint32_t *__restrict__ rank,
                                                        uint32_t *__restrict__ count)
 {
+    GridMeta g;
+    if (partial) {
+        __shared__ GridMeta gs;
+        float4 b = make_float4(INFINITY, INFINITY, -INFINITY, -INFINITY);
+        for (int k = threadIdx.x; k < n_partial; k += kBlock) {
+            const float4 q = partial[k];
+            b.x = fminf(b.x, q.x);
+            b.y = fminf(b.y, q.y);
+            b.z = fmaxf(b.z, q.z);
+            b.w = fmaxf(b.w, q.w);
+        }
+        b = block_bbox<kBlock>(b);
+        if (threadIdx.x == 0) {
+            GridMeta h;
+            grid_geometry(b, rn_dev ? *rn_dev : rn, cs_req, max_cells, h);
+            h.cell_base = 0;
+            h.agent_base = 0;
+            h.n = n;
+            h.seg_end = (uint32_t)n;
+            gs = h;
+            if (blockIdx.x == 0) *meta = h;
+        }
+        __syncthreads();
+        g = gs;
+    } else {
+        g = *meta;
+    }
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    const GridMeta g = *meta;
     const int cx = cell_axis(px[i], g.x0, g.inv_cs, g.nx);
     const int cy = cell_axis(py[i], g.y0, g.inv_cs, g.ny);
     const uint32_t c = (uint32_t)(cx + g.nx * cy);
@@ -100,24 +139,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t *__restri
     if (threadIdx.x == 0) tiles[blockIdx.x] = tot;
 }
 
-// (4b) one block: exclusive scan of the tile sums, in place.
-__global__ __launch_bounds__(kBlock) void k_scan_tiles(uint32_t *__restrict__ tiles,
-                                                       const GridMeta *__restrict__ meta)
-{
-    const int nt = (meta->n_cells + kScanTile - 1) / kScanTile;
-    uint32_t carry = 0;
-    for (int b = 0; b < nt; b += kBlock) {
-        const int t = b + threadIdx.x;
-        const uint32_t v = t < nt ? tiles[t] : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_excl_scan<kBlock>(v, &tot);
-        if (t < nt) tiles[t] = carry + ex;
-        carry += tot;
-        __syncthreads();
-    }
-}
-
-// (4c) exclusive scan inside each tile, offset by the tile's prefix.
+// (4b) exclusive scan inside each tile, offset by the tile's prefix: the sum
+// of the tile sums of (4a) before it, which every block adds up itself (at
+// most a few thousand words from L2, in place of a one-block scan kernel
+// between the two).
 __global__ __launch_bounds__(kBlock) void k_scan_apply(const uint32_t *__restrict__ count,
                                                        const uint32_t *__restrict__ tiles,
                                                        const GridMeta *__restrict__ meta,
@@ -126,6 +151,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const uint32_t *__restric
     const GridMeta g = *meta;
     const int base = blockIdx.x * kScanTile;
     if (base >= g.n_cells) return;
+    uint32_t before = 0;
+    for (int t = threadIdx.x; t < (int)blockIdx.x; t += kBlock) before += tiles[t];
+    uint32_t prefix;
+    block_excl_scan<kBlock>(before, &prefix);
     uint32_t v[kPer];
     uint32_t s = 0;
 #pragma unroll
@@ -135,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const uint32_t *__restric
         s += v[k];
     }
     uint32_t tot;
-    uint32_t run = tiles[blockIdx.x] + block_excl_scan<kBlock>(s, &tot);
+    uint32_t run = prefix + block_excl_scan<kBlock>(s, &tot);
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
         const int c = base + threadIdx.x * kPer + k;
@@ -213,9 +242,12 @@ hipError_t launch_grid_build_rn(const orca_agents_in &in, int n, float rn, float
     const int count_len = (int)L.max_cells;
     hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(kBlock), 0, stream, in.px, in.py, n,
                        w.partial, w.count, count_len);
-    hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(kBlock), 0, stream, w.partial, nbb, rn,
-                       cell_size, count_len, n, rn_dev, w.meta);
-    hipLaunchKernelGGL(k_cell_count, dim3(nb), dim3(kBlock), 0, stream, in.px, in.py, n, w.meta,
+    const bool fused = nbb <= kFusedParts;
+    if (!fused)
+        hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(kBlock), 0, stream, w.partial, nbb, rn,
+                           cell_size, count_len, n, rn_dev, w.meta);
+    hipLaunchKernelGGL(k_cell_count, dim3(nb), dim3(kBlock), 0, stream, in.px, in.py, n,
+                       fused ? w.partial : nullptr, nbb, rn, cell_size, count_len, rn_dev, w.meta,
                        w.cell, w.rank, w.count);
     return launch_scan_scatter(in, n, L, w, w.meta, stream);
 }
@@ -227,7 +259,6 @@ hipError_t launch_scan_scatter(const orca_agents_in &in, int n, const Layout &L,
     const int nt = (int)L.n_tiles;
     hipLaunchKernelGGL(k_scan_reduce, dim3(nt), dim3(kBlock), 0, stream, w.count, scan_meta,
                        w.tiles);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kBlock), 0, stream, w.tiles, scan_meta);
     hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(kBlock), 0, stream, w.count, w.tiles,
                        scan_meta, w.start);
     hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, stream, in, n, w.cell, w.rank,

@@ -262,7 +262,7 @@ struct AdjointBufs {
     uint32_t *e_list;    // 3n
     uint32_t *e_cnt;     // n
     uint32_t *e_start;   // n
-    uint32_t *e_tiles;   // ceil(n / kScanTile) tile prefixes of the count scan
+    uint32_t *e_tiles;   // ceil(n / kScanTile) tile sums of the count scan
     double *tau_blocks;  // kTauBlocks partial sums of the tau contributions
 };
 
