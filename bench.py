@@ -65,14 +65,16 @@ def log(*a):
 
 
 def source_hash(files=("step.hip", "orca_device.h", "orca_internal.h")) -> str:
-    """Hash of a kernel's source files (comments removed, so that only a
-    change of code invalidates the committed counter summaries); by default
-    the step kernel's."""
+    """Hash of a kernel's source files (comments removed and whitespace
+    collapsed, so that only a change of code invalidates the committed
+    counter summaries); by default the step kernel's."""
     h = hashlib.sha256()
     for f in files:
         with open(os.path.join(ROOT, "paper_2008_11578_amd", "csrc", f)) as fh:
             code = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
         code = re.sub(r"//[^\n]*", "", code)
+        # whitespace-insensitive, so that comments of another length leave it
+        code = " ".join(code.split())
         h.update(code.encode())
     return h.hexdigest()[:16]
 

@@ -899,8 +899,9 @@ struct CachedProj {
 // The cache column of this lane for lp3 (CachedProj): the r-th lane of the
 // wavefront that needs LP3 (in lane order) takes the column of the r-th lane
 // that does not; -1 without one.  Every active lane of the wavefront calls
-// it, after its LP2; the columns handed out are not read by their owners
-// again in this step.
+// it, after its LP2.  Only for callers whose lanes read none of their own
+// half-planes after LP2: the step does not, the adjoint's recomputation does
+// (its VJP reads the lines of the active set) and so takes no cache.
 template <int BLOCK>
 __device__ __forceinline__ int lp3_cache_column(bool need, int tid)
 {

@@ -20,12 +20,14 @@ def test_profiles_parse_and_gate_on_source_hash():
     assert len(h) == 16
     t = bench.traffic_from_profile(h)
     v = bench.valu_from_profile(h)
-    if t is not None:   # taken on the current kernel source
-        assert 5e7 < t["bytes"] < 2e8
-        assert t["fetch_kib"] > 0 and t["write_kib"] > 0
-    if v is not None:
-        assert 0 < v["valu_busy_pct"] <= 100 and 0 < v["valu_utilization_pct"] <= 100
-        assert v["valu_insts_per_launch"] > 1e6
+    # the committed summaries were taken on the committed kernel sources
+    assert t is not None and v is not None
+    assert 5e7 < t["bytes"] < 2e8
+    assert t["fetch_kib"] > 0 and t["write_kib"] > 0
+    assert 0 < v["valu_busy_pct"] <= 100 and 0 < v["valu_utilization_pct"] <= 100
+    assert v["valu_insts_per_launch"] > 1e6
+    g = bench.grid_kernels_from_profile(1 << 20, 1 << 21, 0.05)
+    assert g["kernels"] and set(g["kernels"]) >= {"k_cell_count", "k_scatter"}
     # any other source hash turns both off
     assert bench.traffic_from_profile("0" * 16) is None
     assert bench.valu_from_profile("0" * 16) is None
