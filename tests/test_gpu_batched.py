@@ -426,3 +426,41 @@ def test_autotuner_picks_a_valid_configuration_and_caches_it(tmp_path, monkeypat
     assert not r["cached"] and len(r["timings"]) >= len(autotune.FACTORS) + 2
     r2 = autotune.tune_batched(st, off, prm, ws, reps=1)
     assert r2["cached"] and r2["block"] == r["block"] and r2["k_tile"] == r["k_tile"]
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("block", [64, 256])
+def test_batched_lp3_cache_changes_no_result(mode, block):
+    """The batched kernel caches LP3's sub-problem boundaries in the LDS
+    columns of lanes of the same wavefront that run no LP3; a lane finds no
+    such column when most of its wavefront runs LP3.  A jammed scene (most
+    agents in LP3, so many lanes go without), a sparse one (few in LP3, every
+    LP3 lane cached) and one in between must each equal the single-scene
+    step, which never caches, bit for bit, and so must the status bytes."""
+    import torch
+    from paper_2008_11578_amd import orca
+    p = scenarios.Params(dt=0.05, neighbor_dist=5.0, max_neighbors=16)
+    parts = [scenarios.random_state(3000, np.sqrt(3000 / 3.0), seed=91, n_vehicles=150, params=p),
+             scenarios.random_state(1500, np.sqrt(1500 / 0.05), seed=92, params=p),
+             scenarios.random_state(2200, np.sqrt(2200 / 0.6), seed=93, n_vehicles=110, params=p)]
+    off = np.zeros(len(parts) + 1, np.int32)
+    off[1:] = np.cumsum([q.n for q in parts])
+    cat = {k: np.concatenate([getattr(q, k) for q in parts]) for k in parts[0].arrays()}
+    st = orca.State.from_arrays(cat)
+    b = orca.Batch(off, [p] * len(parts), mode=mode, block=block, k_tile=16)
+    status = torch.zeros(st.n, dtype=torch.uint8, device="cuda")
+    out = orca.step_batched(st, b, orca.Workspace(st.n, n_scenes=len(parts)), status=status)
+    torch.cuda.synchronize()
+    assert int(b.error.item()) == 0
+    share = [float(status[off[s]:off[s + 1]].float().mean().item()) for s in range(len(parts))]
+    _share = ", ".join(f"{x:.3f}" for x in share)
+    print(f"mode {mode} block {block}: LP3 share per scene {_share}", flush=True)
+    assert share[0] > 0.6 and share[1] < 0.2
+    for s, q in enumerate(parts):
+        st1 = orca.State.from_arrays(q)
+        status1 = torch.zeros(q.n, dtype=torch.uint8, device="cuda")
+        o1 = orca.step(st1, p, orca.Workspace(q.n), status=status1)
+        torch.cuda.synchronize()
+        for k in ("vx", "vy", "px", "py"):
+            assert torch.equal(getattr(out, k)[off[s]:off[s + 1]], getattr(o1, k)), (s, k)
+        assert torch.equal(status[off[s]:off[s + 1]], status1), s
