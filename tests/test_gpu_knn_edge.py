@@ -119,3 +119,25 @@ def test_edge_candidates_bit_exact(rn, k, n_edge, n_near):
         cur = nxt
     rep, _, _ = compare_step(st, p)
     print("  step", rep, flush=True)
+
+
+@pytest.mark.parametrize("n", [32768, 32769])
+def test_lists_on_both_sides_of_the_fused_grid_setup(n):
+    """Crowds of up to 32,768 agents (at most 128 partial bounding boxes)
+    form the grid geometry inside the counting kernel; one agent more takes
+    the separate setup kernel.  Both give the oracle's neighbour lists bit
+    for bit, from orca_build_grid and from the step's own selection."""
+    import torch
+    from paper_2008_11578_amd import orca
+    sc = scenarios.random_state(n, float(np.sqrt(n / 0.8)), seed=n % 97,
+                                params=scenarios.Params(dt=0.1, neighbor_dist=3.0,
+                                                        max_neighbors=12))
+    st = {k: getattr(sc, k) for k in sc.arrays()}
+    p = sc.params
+    onb, ocn = oracle.knn(st["px"], st["py"], p.neighbor_dist, p.max_neighbors)
+    s = orca.State.from_arrays(st)
+    nb, cn = orca.build_grid(s, p, orca.Workspace(s.n))
+    _, nb2, cn2 = orca.step_nbr(s, p, orca.Workspace(s.n))
+    torch.cuda.synchronize()
+    for a, b in ((cn, ocn), (nb, onb), (cn2, ocn), (nb2, onb)):
+        np.testing.assert_array_equal(a.cpu().numpy(), b)
