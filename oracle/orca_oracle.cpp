@@ -416,7 +416,7 @@ template <class T>
 void lp3(const Line<T> *L, int m, int nh, int fail, double vmax, T tx, T ty, double eps, T *vx,
          T *vy, int64_t *w, Trace &tr)
 {
-    Line<T> proj[ORACLE_K_MAX + ORACLE_HARD];
+    Line<T> proj[ORACLE_K_MAX + ORACLE_HARD]{};
     T level = 0.0;
     T x = *vx, y = *vy;
     for (int i = fail > nh ? fail : nh; i < m; ++i) {
